@@ -1,0 +1,181 @@
+"""FP64 CPU oracle for the potential-field PCG solve (ctypes wrapper).
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The GPU solver
+library shares no code with it.  The arithmetic lives in ``pot3d_oracle.c``,
+which documents the operator, right-hand side and PCG steps with their
+sources in the paper (Sec. 2.1-2.3).
+
+Every function here is pinned by the ``-m "not gpu"`` tests against:
+* closed-form potentials;
+* second-order grid convergence;
+* exact symmetry and definiteness;
+* dense solves on tiny grids;
+* a library CG;
+* conservation and symmetry identities.
+
+Arrays use the phi-fastest C layout: ``x[i, j, k]`` with i radial, j polar and k azimuthal.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pot3d_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, -1, -2, -4, -5
+NCOEF = 8
+DIAG, RM, RP, TM, TP, PM, PP, DTOP = range(NCOEF)
+
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile pot3d_oracle.c into liboracle.so with gcc (OpenMP, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
+                        "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        d = ctypes.POINTER(ctypes.c_double)
+        i = ctypes.c_int
+        lib.orc_assemble.argtypes = [d, i, d, i, d, i, d]
+        lib.orc_assemble.restype = i
+        lib.orc_matvec.argtypes = [i, i, i, d, d, d]
+        lib.orc_matvec.restype = None
+        lib.orc_rhs.argtypes = [d, i, d, i, d, i, d, d]
+        lib.orc_rhs.restype = None
+        lib.orc_dot.argtypes = [d, d, ctypes.c_long]
+        lib.orc_dot.restype = ctypes.c_double
+        lib.orc_pcg.argtypes = [i, i, i, d, d, d, ctypes.c_double, i,
+                                ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        lib.orc_pcg.restype = i
+        lib.orc_true_relres.argtypes = [i, i, i, d, d, d]
+        lib.orc_true_relres.restype = ctypes.c_double
+        lib.orc_pole_values.argtypes = [i, i, i, d, d, d, d]
+        lib.orc_pole_values.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def assemble(rf, tf, pf) -> np.ndarray:
+    """Coefficient arrays (8, nr, nt, np): diag, W_r-, W_r+, W_t-, W_t+, W_p-, W_p+, D_top."""
+    rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
+    nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
+    coef = np.empty((NCOEF, nr, nt, np_))
+    st = _load().orc_assemble(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(coef))
+    if st != OK:
+        raise RuntimeError(f"orc_assemble failed: {st}")
+    return coef
+
+
+def matvec(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
+    _, nr, nt, np_ = coef.shape
+    x = _f64(x).reshape(nr, nt, np_)
+    y = np.empty_like(x)
+    _load().orc_matvec(nr, nt, np_, _p(coef), _p(x), _p(y))
+    return y
+
+
+def rhs(rf, tf, pf, br) -> np.ndarray:
+    rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
+    nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
+    br = _f64(br).reshape(nt, np_)
+    b = np.empty((nr, nt, np_))
+    _load().orc_rhs(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(br), _p(b))
+    return b
+
+
+def dot(a: np.ndarray, b: np.ndarray) -> float:
+    a, b = _f64(a).ravel(), _f64(b).ravel()
+    return float(_load().orc_dot(_p(a), _p(b), a.size))
+
+
+def pcg(coef: np.ndarray, b: np.ndarray, tol: float, maxit: int, x0=None):
+    """Jacobi-PCG.  Returns (x, iters, relres_recursive, status)."""
+    _, nr, nt, np_ = coef.shape
+    b = _f64(b).reshape(nr, nt, np_)
+    x = np.zeros_like(b) if x0 is None else _f64(x0).reshape(nr, nt, np_).copy()
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    st = _load().orc_pcg(nr, nt, np_, _p(coef), _p(b), _p(x), float(tol), int(maxit),
+                         ctypes.byref(it), ctypes.byref(rr))
+    return x, it.value, rr.value, st
+
+
+def true_relres(coef: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:
+    _, nr, nt, np_ = coef.shape
+    return float(_load().orc_true_relres(nr, nt, np_, _p(coef), _p(_f64(b)), _p(_f64(x))))
+
+
+def pole_values(pf, x: np.ndarray):
+    """(north, south), each of length nr: eq. (3) phi-averages on the rings next to the poles."""
+    pf = _f64(pf)
+    x = _f64(x)
+    nr, nt, np_ = x.shape
+    n = np.empty(nr)
+    s = np.empty(nr)
+    _load().orc_pole_values(nr, nt, np_, _p(pf), _p(x), _p(n), _p(s))
+    return n, s
+
+
+def solve(rf, tf, pf, br, tol: float, maxit: int, x0=None):
+    """Assemble, form b and run PCG.  Returns dict with phi, iters, relres, true_relres, status."""
+    coef = assemble(rf, tf, pf)
+    b = rhs(rf, tf, pf, br)
+    x, iters, relres, st = pcg(coef, b, tol, maxit, x0)
+    return {"phi": x, "iters": iters, "relres": relres, "status": st,
+            "true_relres": true_relres(coef, b, x) if np.any(b) else 0.0, "coef": coef, "b": b}
+
+
+def to_sparse(coef: np.ndarray):
+    """The same operator as a scipy CSR matrix, built from the coefficient
+    arrays and the neighbour offsets (phi wraps; r and theta do not)."""
+    import scipy.sparse as sp
+
+    _, nr, nt, np_ = coef.shape
+    n = nr * nt * np_
+    idx = np.arange(n).reshape(nr, nt, np_)
+    rows = [idx.ravel()]
+    cols = [idx.ravel()]
+    vals = [coef[DIAG].ravel()]
+
+    def add(mask_rows, nb, w):
+        rows.append(idx[mask_rows].ravel())
+        cols.append(nb.ravel())
+        vals.append(-w[mask_rows].ravel())
+
+    if nr > 1:
+        add(np.s_[1:, :, :], idx[:-1, :, :], coef[RM])
+        add(np.s_[:-1, :, :], idx[1:, :, :], coef[RP])
+    if nt > 1:
+        add(np.s_[:, 1:, :], idx[:, :-1, :], coef[TM])
+        add(np.s_[:, :-1, :], idx[:, 1:, :], coef[TP])
+    if np_ > 1:
+        add(np.s_[:, :, :], np.roll(idx, 1, axis=2), coef[PM])
+        add(np.s_[:, :, :], np.roll(idx, -1, axis=2), coef[PP])
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    A.sum_duplicates()
+    return A

@@ -1,0 +1,308 @@
+/*
+ * pot3d_oracle.c -- FP64 CPU oracle for the potential-field PCG solve.
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this code.  The GPU solver library neither
+ * links nor calls it, and the two share no source, header or table.
+ *
+ * What it computes, and where each piece comes from in the paper
+ * (Caplan, Mikic & Linker, "From MPI to MPI+OpenACC", arXiv:1709.01126):
+ *
+ *  - The model (Sec. 2.1): Laplace's equation for the potential, eq. (1), on the
+ *    shell R0 <= r <= R1, with
+ *      * the surface condition eq. (2) on r = R0, read here with the sign
+ *        dPhi/dr = -Br (so B = -grad Phi); the paper's +Br convention gives -Phi;
+ *      * the "source surface" condition Phi = 0 on r = R1;
+ *      * periodicity in phi;
+ *      * the polar condition eq. (3), which only defines the value reported at
+ *        the poles (see orc_pole_values).
+ *  - The discretization (Sec. 2.2): the second-order finite-difference
+ *    Laplacian on a nonuniform (r, theta, phi) grid shown after eq. (3).  The
+ *    unknowns sit at cell centres.  The printed scheme omits the spherical
+ *    metric (r^2 on the radial faces, 1/r^2 on the angular terms).  It is
+ *    used here with the metric restored, multiplied by the cell volume
+ *    V = r_i^2 sin(theta_j) dr_i dtheta_j dphi_k and negated.  That gives the
+ *    symmetric positive-definite matrix A that Sec. 2.3 calls for.  The
+ *    paper keeps its boundary conditions out of the stored matrix (Sec. 2.2);
+ *    here the surface data become the right-hand side b, so the matrix form
+ *    A Phi = 0 of Sec. 2.2 reads A Phi = b.
+ *  - The solver (Sec. 2.3): conjugate gradients preconditioned by the inverse
+ *    of the diagonal of A ("PC1", point Jacobi), in the standard form of Saad's
+ *    Algorithm 9.1.  The stopping test is ||r_k||_2 / ||b||_2 <= tol on the
+ *    recursively updated residual (the relative tolerance of Sec. 4.1).
+ *
+ * Storage: A is kept as seven coefficient arrays of length N (the diagonal
+ * and one weight per neighbour direction), the stencil form of the DIA storage
+ * of Sec. 2.2.  The periodic phi neighbour wraps inside a row.  Index
+ * P = (i*nt + j)*np + k, with phi fastest.
+ *
+ * Everything is plain IEEE double arithmetic with separate loops per
+ * operation.  Dot products use Neumaier-compensated sums over a fixed
+ * partition of the index range, so results do not depend on the thread count.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+#define ORC_ENOCONV (-4)
+#define ORC_EBREAKDOWN (-5)
+
+#define ORC_TWO_PI 6.283185307179586476925286766559
+
+/* coefficient array order inside the 8*N block handed to orc_assemble */
+enum { C_DIAG = 0, C_RM, C_RP, C_TM, C_TP, C_PM, C_PP, C_DTOP, C_COUNT };
+
+static long idx3(int i, int j, int k, int nt, int np) { return ((long)i * nt + j) * np + k; }
+
+/* ---------------------------------------------------------------------------
+ * Operator assembly (Sec. 2.2 scheme, metric restored, times the cell volume).
+ *
+ * Cell c of a coordinate with faces f[0..n]: centre x_c = (f[c] + f[c+1]) / 2,
+ * width w_c = f[c+1] - f[c], centre spacing x_{c+1} - x_c.  In phi the spacing
+ * across the periodic seam is x_0 + 2 pi - x_{n-1}.
+ *
+ *   radial face i+1/2 (between centres i, i+1):
+ *       W = dphi_k * sin(theta_j) dtheta_j * rf[i+1]^2 / (r_{i+1} - r_i)
+ *   bottom face r = R0: no coupling (Neumann data go to b)
+ *   top face r = R1, Phi = 0 on the face, one-sided difference over the half cell:
+ *       Dtop = dphi_k * sin(theta_j) dtheta_j * rf[nr]^2 / (rf[nr] - r_{nr-1}), on the diagonal
+ *   polar-angle face j+1/2:  W = dphi_k * dr_i * sin(tf[j+1]) / (theta_{j+1} - theta_j)
+ *   pole faces (theta = 0, pi): sin = 0, so no coupling (set exactly to zero)
+ *   azimuthal face k+1/2:    W = dr_i * dtheta_j / sin(theta_j) / (phi_{k+1} - phi_k)
+ *   diagonal = sum of the neighbour weights present + Dtop
+ * ------------------------------------------------------------------------- */
+int orc_assemble(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, double *coef)
+{
+    if (nr < 1 || nt < 1 || np < 1 || !rf || !tf || !pf || !coef) return ORC_EINVAL;
+    const long N = (long)nr * nt * np;
+    double *rc = malloc(sizeof(double) * nr), *dr = malloc(sizeof(double) * nr);
+    double *tc = malloc(sizeof(double) * nt), *dt = malloc(sizeof(double) * nt);
+    double *pc = malloc(sizeof(double) * np), *dp = malloc(sizeof(double) * np);
+    if (!rc || !dr || !tc || !dt || !pc || !dp) {
+        free(rc); free(dr); free(tc); free(dt); free(pc); free(dp);
+        return ORC_ENOMEM;
+    }
+    for (int i = 0; i < nr; i++) { rc[i] = 0.5 * (rf[i] + rf[i + 1]); dr[i] = rf[i + 1] - rf[i]; }
+    for (int j = 0; j < nt; j++) { tc[j] = 0.5 * (tf[j] + tf[j + 1]); dt[j] = tf[j + 1] - tf[j]; }
+    for (int k = 0; k < np; k++) { pc[k] = 0.5 * (pf[k] + pf[k + 1]); dp[k] = pf[k + 1] - pf[k]; }
+
+    double *D = coef + C_DIAG * N, *WRM = coef + C_RM * N, *WRP = coef + C_RP * N;
+    double *WTM = coef + C_TM * N, *WTP = coef + C_TP * N, *WPM = coef + C_PM * N;
+    double *WPP = coef + C_PP * N, *DTOP = coef + C_DTOP * N;
+
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++) {
+        for (int j = 0; j < nt; j++) {
+            for (int k = 0; k < np; k++) {
+                const long P = idx3(i, j, k, nt, np);
+                const double area_r = dp[k] * sin(tc[j]) * dt[j];   /* angular area of an r-face / r^2 */
+                double wrm = 0.0, wrp = 0.0, wtm = 0.0, wtp = 0.0, dtop = 0.0;
+                if (i > 0)      wrm = area_r * rf[i] * rf[i] / (rc[i] - rc[i - 1]);
+                if (i < nr - 1) wrp = area_r * rf[i + 1] * rf[i + 1] / (rc[i + 1] - rc[i]);
+                if (i == nr - 1) dtop = area_r * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]);
+                if (j > 0)      wtm = dp[k] * dr[i] * sin(tf[j]) / (tc[j] - tc[j - 1]);
+                if (j < nt - 1) wtp = dp[k] * dr[i] * sin(tf[j + 1]) / (tc[j + 1] - tc[j]);
+                double sp_minus = (k > 0) ? pc[k] - pc[k - 1] : pc[0] + ORC_TWO_PI - pc[np - 1];
+                double sp_plus = (k < np - 1) ? pc[k + 1] - pc[k] : pc[0] + ORC_TWO_PI - pc[np - 1];
+                double wpm = 0.0, wpp = 0.0;
+                if (np > 1) {
+                    const double area_p = dr[i] * dt[j] / sin(tc[j]);
+                    wpm = area_p / sp_minus;
+                    wpp = area_p / sp_plus;
+                }
+                WRM[P] = wrm; WRP[P] = wrp; WTM[P] = wtm; WTP[P] = wtp;
+                WPM[P] = wpm; WPP[P] = wpp; DTOP[P] = dtop;
+                D[P] = wrm + wrp + wtm + wtp + wpm + wpp + dtop;
+            }
+        }
+    }
+    free(rc); free(dr); free(tc); free(dt); free(pc); free(dp);
+    return ORC_OK;
+}
+
+/* y = A x: diagonal times the centre minus each neighbour weight times that
+ * neighbour.  Neighbours outside the shell in r or across a pole do not exist
+ * (their weights are zero); phi wraps. */
+void orc_matvec(int nr, int nt, int np, const double *coef, const double *x, double *y)
+{
+    const long N = (long)nr * nt * np;
+    const double *D = coef + C_DIAG * N, *WRM = coef + C_RM * N, *WRP = coef + C_RP * N;
+    const double *WTM = coef + C_TM * N, *WTP = coef + C_TP * N, *WPM = coef + C_PM * N;
+    const double *WPP = coef + C_PP * N;
+    #pragma omp parallel for schedule(static)
+    for (int i = 0; i < nr; i++) {
+        for (int j = 0; j < nt; j++) {
+            for (int k = 0; k < np; k++) {
+                const long P = idx3(i, j, k, nt, np);
+                double s = D[P] * x[P];
+                if (i > 0)      s -= WRM[P] * x[idx3(i - 1, j, k, nt, np)];
+                if (i < nr - 1) s -= WRP[P] * x[idx3(i + 1, j, k, nt, np)];
+                if (j > 0)      s -= WTM[P] * x[idx3(i, j - 1, k, nt, np)];
+                if (j < nt - 1) s -= WTP[P] * x[idx3(i, j + 1, k, nt, np)];
+                if (np > 1) {
+                    const int km = (k == 0) ? np - 1 : k - 1;
+                    const int kp = (k == np - 1) ? 0 : k + 1;
+                    s -= WPM[P] * x[idx3(i, j, km, nt, np)];
+                    s -= WPP[P] * x[idx3(i, j, kp, nt, np)];
+                }
+                y[P] = s;
+            }
+        }
+    }
+}
+
+/* Right-hand side: the surface condition eq. (2) as a flux through the r = R0
+ * face of the first cell layer.  With dPhi/dr = -Br that flux, times -1 for the
+ * negated operator, is  b = dphi_k sin(theta_j) dtheta_j R0^2 Br(j,k)  on i = 0,
+ * and b = 0 elsewhere.  This is the finite-volume form of the paper's
+ * ghost-cell fill (Sec. 3.5), which sets the ghost layer from Br times the
+ * first radial spacing. */
+void orc_rhs(const double *rf, int nr, const double *tf, int nt, const double *pf, int np,
+             const double *br, double *b)
+{
+    const long N = (long)nr * nt * np;
+    memset(b, 0, sizeof(double) * N);
+    for (int j = 0; j < nt; j++) {
+        const double tcj = 0.5 * (tf[j] + tf[j + 1]), dtj = tf[j + 1] - tf[j];
+        for (int k = 0; k < np; k++) {
+            const double dpk = pf[k + 1] - pf[k];
+            b[idx3(0, j, k, nt, np)] = dpk * sin(tcj) * dtj * rf[0] * rf[0] * br[(long)j * np + k];
+        }
+    }
+}
+
+/* ---- compensated dot over a fixed partition (deterministic for any thread count) */
+#define ORC_CHUNKS 256
+
+static void neumaier_add(double *sum, double *comp, double v)
+{
+    const double t = *sum + v;
+    if (fabs(*sum) >= fabs(v)) *comp += (*sum - t) + v;
+    else                       *comp += (v - t) + *sum;
+    *sum = t;
+}
+
+double orc_dot(const double *a, const double *b, long n)
+{
+    double s[ORC_CHUNKS], c[ORC_CHUNKS];
+    #pragma omp parallel for schedule(static)
+    for (int t = 0; t < ORC_CHUNKS; t++) {
+        const long lo = n * t / ORC_CHUNKS, hi = n * (t + 1) / ORC_CHUNKS;
+        double sum = 0.0, comp = 0.0;
+        for (long q = lo; q < hi; q++) neumaier_add(&sum, &comp, a[q] * b[q]);
+        s[t] = sum;
+        c[t] = comp;
+    }
+    double sum = 0.0, comp = 0.0;
+    for (int t = 0; t < ORC_CHUNKS; t++) {
+        neumaier_add(&sum, &comp, s[t]);
+        neumaier_add(&sum, &comp, c[t]);
+    }
+    return sum + comp;
+}
+
+/* ---------------------------------------------------------------------------
+ * Jacobi-preconditioned CG (Sec. 2.3; Saad, Algorithm 9.1 with M = diag(A)).
+ *
+ *   x = x0; r = b - A x; z = r / d; p = z; rho = r.z
+ *   for k = 1 .. maxit:
+ *       q = A p; sigma = p.q          (sigma <= 0 or not finite: breakdown)
+ *       alpha = rho / sigma; x += alpha p; r -= alpha q
+ *       stop when ||r|| / ||b|| <= tol (iters = k)
+ *       z = r / d; rho' = r.z; beta = rho' / rho; rho = rho'; p = z + beta p
+ *
+ * x holds x0 on entry (zeros for a cold start) and the last iterate on exit.
+ * ||b|| = 0 gives x = 0, iters = 0.  A start that already meets tol returns
+ * iters = 0.  Non-finite data give ORC_EBREAKDOWN with the last finite
+ * iterate.  tol = 0 runs exactly maxit iterations (fixed-count mode).
+ * ------------------------------------------------------------------------- */
+int orc_pcg(int nr, int nt, int np, const double *coef, const double *b, double *x,
+            double tol, int maxit, int *iters_out, double *relres_out)
+{
+    const long N = (long)nr * nt * np;
+    const double *D = coef + C_DIAG * N;
+    double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
+    double *p = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
+    int status = ORC_OK, iters = 0;
+    double relres = 0.0;
+    if (!r || !z || !p || !q) { status = ORC_ENOMEM; goto done; }
+
+    const double nb = sqrt(orc_dot(b, b, N));
+    if (!isfinite(nb)) { status = ORC_EBREAKDOWN; relres = NAN; goto done; }
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * N);
+        goto done;
+    }
+    orc_matvec(nr, nt, np, coef, x, q);
+    #pragma omp parallel for schedule(static)
+    for (long P = 0; P < N; P++) r[P] = b[P] - q[P];
+    relres = sqrt(orc_dot(r, r, N)) / nb;
+    if (!isfinite(relres)) { status = ORC_EBREAKDOWN; goto done; }
+    if (relres <= tol) goto done;
+
+    #pragma omp parallel for schedule(static)
+    for (long P = 0; P < N; P++) { z[P] = r[P] / D[P]; p[P] = z[P]; }
+    double rho = orc_dot(r, z, N);
+
+    status = ORC_ENOCONV;
+    for (int k = 1; k <= maxit; k++) {
+        orc_matvec(nr, nt, np, coef, p, q);
+        const double sigma = orc_dot(p, q, N);
+        if (!(sigma > 0.0) || !isfinite(sigma)) { status = ORC_EBREAKDOWN; break; }
+        const double alpha = rho / sigma;
+        #pragma omp parallel for schedule(static)
+        for (long P = 0; P < N; P++) { x[P] += alpha * p[P]; r[P] -= alpha * q[P]; }
+        iters = k;
+        relres = sqrt(orc_dot(r, r, N)) / nb;
+        if (!isfinite(relres)) { status = ORC_EBREAKDOWN; break; }
+        if (relres <= tol) { status = ORC_OK; break; }
+        #pragma omp parallel for schedule(static)
+        for (long P = 0; P < N; P++) z[P] = r[P] / D[P];
+        const double rho_new = orc_dot(r, z, N);
+        const double beta = rho_new / rho;
+        rho = rho_new;
+        #pragma omp parallel for schedule(static)
+        for (long P = 0; P < N; P++) p[P] = z[P] + beta * p[P];
+    }
+done:
+    free(r); free(z); free(p); free(q);
+    if (iters_out) *iters_out = iters;
+    if (relres_out) *relres_out = relres;
+    return status;
+}
+
+/* ||b - A x||_2 / ||b||_2 (the true relative residual). */
+double orc_true_relres(int nr, int nt, int np, const double *coef, const double *b, const double *x)
+{
+    const long N = (long)nr * nt * np;
+    double *q = malloc(sizeof(double) * N);
+    if (!q) return NAN;
+    orc_matvec(nr, nt, np, coef, x, q);
+    #pragma omp parallel for schedule(static)
+    for (long P = 0; P < N; P++) q[P] = b[P] - q[P];
+    const double num = sqrt(orc_dot(q, q, N)), den = sqrt(orc_dot(b, b, N));
+    free(q);
+    return num / den;
+}
+
+/* Pole values, eq. (3): the phi-average of Phi on the ring of cell centres
+ * half a pole cell away from the pole (j = 0 for theta = 0, j = nt-1 for
+ * theta = pi), one value per radial layer:
+ *   Phi_pole(i) = (1 / 2 pi) sum_k dphi_k Phi(i, ring, k). */
+void orc_pole_values(int nr, int nt, int np, const double *pf, const double *x, double *north, double *south)
+{
+    const double span = pf[np] - pf[0];
+    for (int i = 0; i < nr; i++) {
+        double sn = 0.0, ss = 0.0;
+        for (int k = 0; k < np; k++) {
+            const double dpk = pf[k + 1] - pf[k];
+            sn += dpk * x[idx3(i, 0, k, nt, np)];
+            ss += dpk * x[idx3(i, nt - 1, k, nt, np)];
+        }
+        north[i] = sn / span;
+        south[i] = ss / span;
+    }
+}
