@@ -1,0 +1,176 @@
+/*
+ * pot3d.h -- C ABI of the MI355X potential-field solver.
+ *
+ * The library solves Laplace's equation for the magnetic potential Phi on a
+ * spherical shell 1 = R0 <= r <= R1 (Caplan, Mikic & Linker,
+ * arXiv:1709.01126, Sec. 2.1, eq. (1)).  The boundary conditions are:
+ *   * r = R0: the surface condition eq. (2), read as dPhi/dr = -Br, so that
+ *     B = -grad Phi.  The paper writes B = +grad Phi with dPhi/dr = +Br; its
+ *     potential is the negative of the one returned here;
+ *   * r = R1: the "source surface" Phi = 0 (Sec. 2.1);
+ *   * phi: periodic;
+ *   * poles: eq. (3) only defines the value reported there, see
+ *     pot3d_pole_values.
+ *
+ * Discretization (Sec. 2.2): the second-order finite-difference Laplacian on
+ * a nonuniform, logically rectangular (r, theta, phi) grid, with unknowns at
+ * cell centres.  It is used in its symmetric finite-volume form: spherical
+ * metric restored, scaled by the cell volume, negated.  That gives the
+ * symmetric positive-definite system A Phi = b, where b carries the surface
+ * flux of Br.
+ *
+ * Solver (Sec. 2.3): conjugate gradients with the point-Jacobi
+ * preconditioner (the inverse of the diagonal of A, "PC1").  It stops when
+ * ||r_k||_2 / ||b||_2 <= tol on the recursively updated residual, the
+ * relative tolerance of Sec. 4.1.
+ *
+ * Layouts: every 3-D array is C order with phi fastest,
+ *     a[(i*nt + j)*np + k],  i radial, j polar (from theta = 0), k azimuthal,
+ * and every surface map is br[j*np + k], sampled at the angular cell centres.
+ *
+ * Ownership: the caller owns every buffer passed in.  The library copies the
+ * faces at create time and reads Br and Phi0 during a call only.  It keeps
+ * all of its device memory in the context until pot3d_destroy.
+ *
+ * Errors: every int-returning call returns a POT3D_* status.  Argument
+ * checks run before any device call, so POT3D_EINVAL paths work without a
+ * GPU.  pot3d_last_error gives a readable message.  A context is not
+ * thread-safe; distinct contexts may be used from different threads.
+ */
+#ifndef POT3D_H
+#define POT3D_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pot3d_ctx pot3d_ctx;
+
+enum pot3d_status {
+    POT3D_OK = 0,
+    POT3D_EINVAL = -1,      /* bad argument; nothing was done                           */
+    POT3D_ENOMEM = -2,      /* device or host allocation failed                         */
+    POT3D_EDEVICE = -3,     /* HIP runtime error (no device, launch failure, ...)       */
+    POT3D_ENOCONV = -4,     /* maxit reached; Phi, iters, relres hold the last iterate  */
+    POT3D_EBREAKDOWN = -5   /* non-finite data or p.Ap <= 0; the last finite iterate
+                               is returned                                             */
+};
+
+enum pot3d_upper_bc {
+    POT3D_UPPER_SOURCE_SURFACE = 0,   /* Phi(R1) = 0 (Sec. 2.1)                                   */
+    POT3D_UPPER_CLOSED_WALL = 1       /* Br(R1) = 0 (Sec. 2.1); singular system, not supported:
+                                         POT3D_EINVAL                                            */
+};
+
+enum pot3d_precision {
+    POT3D_FP64 = 0,          /* FP64 vectors, stencil and reductions throughout              */
+    POT3D_FP32_REFINED = 1   /* FP32 inner PCG inside FP64 defect correction (see
+                                pot3d_solve_device)                                        */
+};
+
+typedef struct pot3d_stats {
+    int iters;               /* PCG iterations of the last solve (inner iterations summed
+                                in refined mode)                                           */
+    int outer;               /* defect-correction cycles (1 in FP64 mode)                    */
+    int status;              /* status of the last solve                                    */
+    int graph_launches;      /* replays of the captured iteration graph                     */
+    double relres;           /* recursive ||r||/||b|| at exit (FP64 mode)                   */
+    double relres_true;      /* ||b - A Phi||/||b||, recomputed in FP64 at exit             */
+    double solve_ms;         /* wall time of the last solve call on the device             */
+    double loop_ms;          /* device time of the iteration loop (hipEvents)               */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 64 N (FP64), 32 N
+                                (FP32 inner)                                               */
+    long long n;             /* unknowns nr*nt*np                                            */
+    int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
+    int tile_j, chunk_i;     /* launch shape of the stencil kernels                         */
+    int blocks;              /* workgroups per stencil launch                               */
+} pot3d_stats;
+
+/*
+ * Create a solver context for one grid (Sec. 2.2 mesh), on HIP device `device`.
+ *   r_faces[0..nr]   strictly increasing, r_faces[0] > 0 (R0 = r_faces[0], R1 = r_faces[nr])
+ *   t_faces[0..nt]   strictly increasing polar faces, t_faces[0] = 0, t_faces[nt] = pi
+ *   p_faces[0..np]   strictly increasing azimuthal faces, p_faces[np] - p_faces[0] = 2 pi
+ *   nr >= 2, nt >= 2, np >= 3.  Arrays are host memory, copied.
+ *   upper_bc   POT3D_UPPER_SOURCE_SURFACE (closed wall is rejected with POT3D_EINVAL)
+ *   precision  POT3D_FP64 or POT3D_FP32_REFINED
+ * On success *out owns device buffers of about 32 N + (FP32 mode) 16 N bytes.
+ */
+int pot3d_create(const double *r_faces, int nr,
+                 const double *t_faces, int nt,
+                 const double *p_faces, int np,
+                 int upper_bc, int precision, int device, pot3d_ctx **out);
+
+/*
+ * Solve A Phi = b(Br) from host memory (Sec. 2.1-2.3).
+ *   br     host, nt*np, br[j*np + k]: Br at the angular cell centres of r = R0
+ *   tol    >= 0; stop when ||r||/||b|| <= tol; tol = 0 runs exactly maxit iterations
+ *   maxit  >= 0 iteration cap
+ *   phi0   host, N, initial guess; NULL starts from zero
+ *   phi    host, N, out: the solution (also filled on ENOCONV / EBREAKDOWN)
+ *   iters  out (may be NULL): iterations performed
+ *   relres_true out (may be NULL): ||b - A Phi||_2 / ||b||_2 recomputed at exit
+ * Includes the host<->device copies of Br, Phi0 and Phi.
+ */
+int pot3d_solve(pot3d_ctx *ctx, const double *br, double tol, int maxit,
+                const double *phi0, double *phi, int *iters, double *relres_true);
+
+/*
+ * As pot3d_solve, with device buffers and the caller's HIP stream
+ * (hipStream_t passed as void*; NULL = the context's own stream).
+ *   d_br   device, nt*np;  d_phi0 device, N or NULL;  d_phi device, N, out.
+ * All work is ordered on `stream`; the call returns after the solve has
+ * finished (it waits on the stream for the convergence flag).
+ * In POT3D_FP32_REFINED contexts the outer loop recomputes r = b - A Phi in
+ * FP64, solves A e = r with FP32 PCG to inner_tol (1e-5), and adds e to Phi in
+ * FP64.  It repeats until the FP64 true residual is <= tol.
+ */
+int pot3d_solve_device(pot3d_ctx *ctx, const double *d_br, const double *d_phi0, double *d_phi,
+                       void *stream, double tol, int maxit, int *iters, double *relres_true);
+
+/*
+ * y = A x with the solver's own stencil (the Sec. 2.2 operator, volume-scaled).
+ * d_x, d_y: device, N each, phi-fastest, distinct.  Ordered on `stream`
+ * (NULL = the context's stream); returns after the kernel has completed.
+ */
+int pot3d_apply_device(pot3d_ctx *ctx, const double *d_x, double *d_y, void *stream);
+
+/*
+ * Right-hand side b (device, N): the surface flux of Br through the r = R0
+ * faces on the first radial layer, zero elsewhere (eq. (2) as a boundary flux).
+ */
+int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stream);
+
+/*
+ * Pole values of the last solution, eq. (3): for each radial layer, the
+ * phi-average of Phi on the ring of cell centres half a pole cell from the
+ * pole.  north, south: host, nr each.
+ */
+int pot3d_pole_values(const pot3d_ctx *ctx, double *north, double *south);
+
+/* Statistics of the last solve. */
+int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
+
+/*
+ * Benchmark helper: launch the two per-iteration stencil kernels (the p
+ * update with A p and p.Ap, then the r/x update with r.z and r.r) `reps` times
+ * each, back to back on the context's stream, and report each kernel's
+ * average duration in ms from hipEvents.  It runs on the vectors the context
+ * holds and overwrites them; a later solve re-initializes everything.
+ */
+int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
+
+/* Free the context and all of its device memory.  NULL is a no-op. */
+void pot3d_destroy(pot3d_ctx *ctx);
+
+/* Message of the last error on ctx (ctx = NULL: the calling thread's last
+ * create/validation error).  Never NULL; valid until the next call. */
+const char *pot3d_last_error(const pot3d_ctx *ctx);
+
+/* Library version string. */
+const char *pot3d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POT3D_H */

@@ -1,0 +1,10 @@
+"""MI355X-native FP64 point-Jacobi PCG for the spherical Laplace equation
+(the potential-field solve of arXiv:1709.01126, Sec. 2).
+
+The solver is the C-ABI library ``libpot3d.so``.  Its hand-written gfx950
+kernels are in ``csrc/`` and its interface is in ``include/pot3d.h``.
+``pot3d`` is the ctypes binding.  PyTorch is only used by callers for device
+buffers and streams.
+"""
+from .pot3d import (EBREAKDOWN, EDEVICE, EINVAL, ENOCONV, ENOMEM, FP32_REFINED, FP64, OK,  # noqa: F401
+                    UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Solver, load)

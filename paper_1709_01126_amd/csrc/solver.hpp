@@ -1,0 +1,84 @@
+// solver.hpp -- internal types shared by the HIP kernels and the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pot3d {
+
+// Tile shape of the stencil kernels: a workgroup of 4 wavefronts owns a
+// TJ (polar rows) x 64 (azimuthal cells) column of the grid and walks a chunk of
+// radial layers.
+constexpr int kWave = 64;
+constexpr int kWaves = 4;
+constexpr int kThreads = kWave * kWaves;
+constexpr int kXcds = 8;   // MI355X: consecutive workgroups go round-robin to 8 XCDs
+
+// Per (i, j) row of the grid: the weights of the volume-scaled operator that
+// are constant along phi, in units that the per-k factors complete:
+//   W_r-  = dphi_k * rm      W_r+  = dphi_k * rp
+//   W_t-  = dphi_k * tm      W_t+  = dphi_k * tp
+//   W_p-  = pq / (phi_k - phi_{k-1})   W_p+ = pq / (phi_{k+1} - phi_k)
+//   diag  = dphi_k * s + pq * (1/(phi_k - phi_{k-1}) + 1/(phi_{k+1} - phi_k))
+// with s = rm + rp + tm + tp + (top layer) D_top / dphi_k.
+struct alignas(64) RowCoef {
+    double rm, rp, tm, tp, s, pq, pad0, pad1;
+};
+
+// Device-resident scalars of one PCG solve.  Kernels read them, so the
+// iteration needs no host round trip and can be replayed from a graph.
+struct alignas(64) DevScalars {
+    double rho;        // r.z of the current residual
+    double alpha;      // step length of the current iteration
+    double beta;       // rho_k / rho_{k-1} for the next search direction
+    double sigma;      // p.Ap
+    double rr;         // r.r
+    double bnorm;      // ||b||_2
+    double relres;     // ||r||_2 / ||b||_2 (recursive)
+    double tol;        // stopping tolerance
+    double bb;         // b.b
+    double relres_true;
+    int k;             // iterations done
+    int maxit;
+    int done;          // 1: all further iteration kernels are no-ops
+    int status;        // POT3D_* status once done
+    int zero_solution; // ||b|| = 0: the answer is Phi = 0
+    int pad[3];
+};
+
+// Launch geometry and tables common to every stencil launch.
+struct GridArgs {
+    int nr, nt, np, pitch;
+    long long plane;      // nt * pitch elements
+    int ci;               // radial layers per workgroup chunk
+    int nchunk, ntj, ntk; // chunks along r, tiles along theta and phi
+    int nblocks;
+    const RowCoef *rows;  // nr * nt
+    const double *dphi;   // np: phi_f[k+1] - phi_f[k]
+    const double *ih;     // np: 1 / (phi_{k+1} - phi_k), wrapping at k = np-1
+};
+
+enum Mode : int {
+    kApply = 0,   // y = A x
+    kResidual = 1,// r = b - A x (optional store); partials r.z, r.r, b.b
+    kUpdateP = 2, // p = D^-1 r + beta p_old (stored); partial p.Ap
+    kUpdateR = 3  // r -= alpha A p; x += alpha p; partials r.z, r.r
+};
+
+template <typename V>
+struct StencilVecs {
+    const V *in;      // operand: x (apply, residual), p (update-r), r (update-p)
+    const V *pold;    // update-p: previous search direction
+    V *pnew;          // update-p: new search direction (stored)
+    V *r;             // residual: out; update-r: in/out
+    V *x;             // update-r: in/out
+    V *y;             // apply: out
+    const double *bplane;  // residual: b on the first radial layer (nt * pitch)
+    const DevScalars *sc;
+    double *partial;  // [3][nblocks] per-workgroup partial sums
+    int store_r;      // residual: 1 to store r, 0 to reduce only
+    int ignore_done;  // 1: run even when sc->done is set
+};
+
+}  // namespace pot3d

@@ -1,0 +1,251 @@
+"""ctypes binding of libpot3d.so (include/pot3d.h).  Argument marshalling only.
+
+Every function keeps the C name and argument order.  Host arrays are numpy
+float64 C-contiguous arrays.  Device buffers and streams are passed as
+integers: ``tensor.data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``.
+There is no CPU fallback.  If the library is not built, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpot3d.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
+UPPER_SOURCE_SURFACE, UPPER_CLOSED_WALL = 0, 1
+FP64, FP32_REFINED = 0, 1
+STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
+                EBREAKDOWN: "EBREAKDOWN"}
+
+EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
+            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_destroy", "pot3d_last_error",
+            "pot3d_version")
+
+
+class pot3d_stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("status", ctypes.c_int),
+                ("graph_launches", ctypes.c_int), ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("loop_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
+                ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_j", ctypes.c_int),
+                ("chunk_i", ctypes.c_int), ("blocks", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpot3d.so.  Raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1709_01126_amd.build` "
+                          "(or __graft_entry__.build()); there is no CPU fallback")
+    lib = ctypes.CDLL(path)
+    d = ctypes.POINTER(ctypes.c_double)
+    vp = ctypes.c_void_p
+    i = ctypes.c_int
+    lib.pot3d_create.argtypes = [d, i, d, i, d, i, i, i, i, ctypes.POINTER(vp)]
+    lib.pot3d_create.restype = i
+    lib.pot3d_solve.argtypes = [vp, d, ctypes.c_double, i, d, d, ctypes.POINTER(i), d]
+    lib.pot3d_solve.restype = i
+    lib.pot3d_solve_device.argtypes = [vp, vp, vp, vp, vp, ctypes.c_double, i, ctypes.POINTER(i), d]
+    lib.pot3d_solve_device.restype = i
+    lib.pot3d_apply_device.argtypes = [vp, vp, vp, vp]
+    lib.pot3d_apply_device.restype = i
+    lib.pot3d_rhs_device.argtypes = [vp, vp, vp, vp]
+    lib.pot3d_rhs_device.restype = i
+    lib.pot3d_pole_values.argtypes = [vp, d, d]
+    lib.pot3d_pole_values.restype = i
+    lib.pot3d_get_stats.argtypes = [vp, ctypes.POINTER(pot3d_stats)]
+    lib.pot3d_get_stats.restype = i
+    lib.pot3d_time_kernels.argtypes = [vp, i, d, d]
+    lib.pot3d_time_kernels.restype = i
+    lib.pot3d_destroy.argtypes = [vp]
+    lib.pot3d_destroy.restype = None
+    lib.pot3d_last_error.argtypes = [vp]
+    lib.pot3d_last_error.restype = ctypes.c_char_p
+    lib.pot3d_version.argtypes = []
+    lib.pot3d_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _dp(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Pot3dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def pot3d_version() -> str:
+    return load().pot3d_version().decode()
+
+
+def pot3d_last_error(ctx=None) -> str:
+    return load().pot3d_last_error(ctx).decode()
+
+
+def pot3d_create(r_faces, t_faces, p_faces, upper_bc=UPPER_SOURCE_SURFACE, precision=FP64, device=0):
+    """Returns (status, ctx handle or None)."""
+    rf, tf, pf = _f64(r_faces), _f64(t_faces), _f64(p_faces)
+    out = ctypes.c_void_p(None)
+    st = load().pot3d_create(_dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1,
+                             int(upper_bc), int(precision), int(device), ctypes.byref(out))
+    return st, (out.value if st == OK else None)
+
+
+def pot3d_solve(ctx, br, tol, maxit, phi0, phi_out):
+    """Host solve.  phi_out: preallocated float64 array of N.  Returns (status, iters, relres_true)."""
+    br = _f64(br)
+    phi0 = _f64(phi0)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    st = load().pot3d_solve(ctx, _dp(br), float(tol), int(maxit), _dp(phi0), _dp(phi_out), ctypes.byref(it),
+                            ctypes.byref(rr))
+    return st, it.value, rr.value
+
+
+def pot3d_solve_device(ctx, d_br, d_phi0, d_phi, stream, tol, maxit):
+    """Device solve on device pointers (ints).  Returns (status, iters, relres_true)."""
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    st = load().pot3d_solve_device(ctx, d_br, d_phi0, d_phi, stream, float(tol), int(maxit), ctypes.byref(it),
+                                   ctypes.byref(rr))
+    return st, it.value, rr.value
+
+
+def pot3d_apply_device(ctx, d_x, d_y, stream=None):
+    return load().pot3d_apply_device(ctx, d_x, d_y, stream)
+
+
+def pot3d_rhs_device(ctx, d_br, d_b, stream=None):
+    return load().pot3d_rhs_device(ctx, d_br, d_b, stream)
+
+
+def pot3d_pole_values(ctx, nr):
+    north = np.empty(nr)
+    south = np.empty(nr)
+    st = load().pot3d_pole_values(ctx, _dp(north), _dp(south))
+    return st, north, south
+
+
+def pot3d_get_stats(ctx):
+    s = pot3d_stats()
+    st = load().pot3d_get_stats(ctx, ctypes.byref(s))
+    return st, s.as_dict()
+
+
+def pot3d_time_kernels(ctx, reps):
+    a = ctypes.c_double(0.0)
+    b = ctypes.c_double(0.0)
+    st = load().pot3d_time_kernels(ctx, int(reps), ctypes.byref(a), ctypes.byref(b))
+    return st, a.value, b.value
+
+
+def pot3d_destroy(ctx):
+    if ctx:
+        load().pot3d_destroy(ctx)
+
+
+class Solver:
+    """Owns one context; raises Pot3dError on EINVAL/ENOMEM/EDEVICE."""
+
+    def __init__(self, r_faces, t_faces, p_faces, upper_bc=UPPER_SOURCE_SURFACE, precision=FP64, device=0):
+        st, ctx = pot3d_create(r_faces, t_faces, p_faces, upper_bc, precision, device)
+        if st != OK:
+            raise Pot3dError(st, pot3d_last_error(None))
+        self.ctx = ctx
+        self.nr, self.nt, self.np = len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1
+
+    @property
+    def shape(self):
+        return (self.nr, self.nt, self.np)
+
+    def _check(self, st, allowed=(OK, ENOCONV, EBREAKDOWN)):
+        if st not in allowed:
+            raise Pot3dError(st, pot3d_last_error(self.ctx))
+        return st
+
+    def solve(self, br, tol, maxit, phi0=None):
+        """Host arrays in, host Phi out.  Returns (phi, status, iters, relres_true)."""
+        phi = np.empty(self.shape)
+        st, it, rr = pot3d_solve(self.ctx, br, tol, maxit, phi0, phi)
+        self._check(st)
+        return phi, st, it, rr
+
+    def solve_device(self, br, phi, tol, maxit, phi0=None, stream=None):
+        """torch CUDA float64 tensors in/out on the given (or current) stream."""
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(br.device)
+        for t in (br, phi) + ((phi0,) if phi0 is not None else ()):
+            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+        st, it, rr = pot3d_solve_device(self.ctx, br.data_ptr(), phi0.data_ptr() if phi0 is not None else None,
+                                        phi.data_ptr(), stream.cuda_stream, tol, maxit)
+        self._check(st)
+        return st, it, rr
+
+    def apply(self, x, y, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(x.device)
+        self._check(pot3d_apply_device(self.ctx, x.data_ptr(), y.data_ptr(), stream.cuda_stream), (OK,))
+
+    def rhs(self, br, b, stream=None):
+        import torch
+
+        if stream is None:
+            stream = torch.cuda.current_stream(br.device)
+        self._check(pot3d_rhs_device(self.ctx, br.data_ptr(), b.data_ptr(), stream.cuda_stream), (OK,))
+
+    def pole_values(self):
+        st, n, s = pot3d_pole_values(self.ctx, self.nr)
+        self._check(st, (OK,))
+        return n, s
+
+    def stats(self):
+        st, s = pot3d_get_stats(self.ctx)
+        self._check(st, (OK,))
+        return s
+
+    def time_kernels(self, reps):
+        st, a, b = pot3d_time_kernels(self.ctx, reps)
+        self._check(st, (OK,))
+        return a, b
+
+    def close(self):
+        if self.ctx:
+            pot3d_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

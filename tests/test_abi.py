@@ -1,0 +1,111 @@
+"""C-ABI library: loads, exports every declared entry point, rejects bad
+arguments before touching a device (CPU only; no compute calls)."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1709_01126_amd import pot3d as P
+from workloads import grids
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pot3d.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*(pot3d_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_destroy", "pot3d_last_error"):
+        assert n in names
+    assert set(names) == set(P.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.load()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", P.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pot3d_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_version():
+    assert "gfx950" in P.pot3d_version()
+
+
+def good_faces():
+    return grids.r_faces_stretched(4), grids.theta_faces_ratio3(6), grids.phi_faces_uniform(8)
+
+
+def create_status(rf, tf, pf, upper=0, prec=0):
+    st, ctx = P.pot3d_create(rf, tf, pf, upper, prec, 0)
+    assert ctx is None
+    return st
+
+
+@pytest.mark.parametrize("mutate", [
+    "r_nonmonotone", "r_nan", "r_nonpositive", "t_not_zero", "t_not_pi", "t_nonmonotone",
+    "p_span", "p_nonmonotone", "nr_small", "nt_small", "np_small", "closed_wall", "bad_upper", "bad_precision",
+])
+def test_create_rejects_invalid_input(mutate):
+    rf, tf, pf = good_faces()
+    rf, tf, pf = rf.copy(), tf.copy(), pf.copy()
+    upper, prec = 0, 0
+    if mutate == "r_nonmonotone":
+        rf[2] = rf[1]
+    elif mutate == "r_nan":
+        rf[3] = np.nan
+    elif mutate == "r_nonpositive":
+        rf = rf - 2.0
+    elif mutate == "t_not_zero":
+        tf[0] = 0.01
+    elif mutate == "t_not_pi":
+        tf[-1] = math.pi - 0.01
+    elif mutate == "t_nonmonotone":
+        tf[2], tf[3] = tf[3], tf[2]
+    elif mutate == "p_span":
+        pf = pf * 0.5
+    elif mutate == "p_nonmonotone":
+        pf[4] = pf[3]
+    elif mutate == "nr_small":
+        rf = rf[:2]
+    elif mutate == "nt_small":
+        tf = np.array([0.0, math.pi])
+    elif mutate == "np_small":
+        pf = np.array([0.0, math.pi, 2 * math.pi])
+    elif mutate == "closed_wall":
+        upper = P.UPPER_CLOSED_WALL
+    elif mutate == "bad_upper":
+        upper = 7
+    elif mutate == "bad_precision":
+        prec = 9
+    assert create_status(rf, tf, pf, upper, prec) == P.EINVAL
+    assert P.pot3d_last_error(None) != ""
+
+
+def test_null_arguments():
+    lib = P.load()
+    out = ctypes.c_void_p(None)
+    d = ctypes.POINTER(ctypes.c_double)()
+    assert lib.pot3d_create(d, 4, d, 6, d, 8, 0, 0, 0, ctypes.byref(out)) == P.EINVAL
+    rf, tf, pf = good_faces()
+    assert lib.pot3d_create(P._dp(rf), 4, P._dp(tf), 6, P._dp(pf), 8, 0, 0, 0, None) == P.EINVAL
+    phi = np.empty(4 * 6 * 8)
+    br = np.zeros(6 * 8)
+    assert P.pot3d_solve(None, br, 1e-10, 10, None, phi)[0] == P.EINVAL
+    assert P.pot3d_solve_device(None, 1, None, 1, None, 1e-10, 10)[0] == P.EINVAL
+    assert P.pot3d_apply_device(None, 1, 2) == P.EINVAL
+    assert P.pot3d_rhs_device(None, 1, 2) == P.EINVAL
+    assert P.pot3d_pole_values(None, 4)[0] == P.EINVAL
+    assert P.pot3d_get_stats(None)[0] == P.EINVAL
+    assert P.pot3d_time_kernels(None, 3)[0] == P.EINVAL
+    P.pot3d_destroy(None)
