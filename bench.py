@@ -58,16 +58,25 @@ def load_traffic(workload: str, kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def kernel_name(stats, which):
+    tile = stats["tile_p"] if which == "update_p" else stats["tile_r"]
+    mode = 2 if which == "update_p" else 3
+    if tile > 100:
+        return f"stencil_wave<{tile - 100},{mode},double>"
+    return f"stencil_march<{tile},{mode},double>"
+
+
 def cpu_baseline(w, faces, br, budget_s: float):
     import oracle
 
     rf, tf, pf = faces
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
-    # one short run to size the sample, then a run of about budget_s seconds
+    # a warm-up run, a short run to size the sample, then a run of about budget_s seconds
+    oracle.pcg(coef, b, 0.0, 1)
     t0 = time.perf_counter()
-    oracle.pcg(coef, b, 0.0, 2)
-    per = max(1e-3, (time.perf_counter() - t0) / 2)
+    oracle.pcg(coef, b, 0.0, 5)
+    per = max(1e-3, (time.perf_counter() - t0) / 5)
     k = max(3, int(budget_s / per))
     t0 = time.perf_counter()
     _, iters, _, _ = oracle.pcg(coef, b, 0.0, k)
@@ -87,6 +96,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="short run for hardware counters: a few iterations, the two stencil kernels "
+                         "--kernel-reps times each, and one device copy of N doubles (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this solver runs on a single device (asked for --gpus {args.gpus}); "
@@ -109,6 +121,18 @@ def main():
     d_br = torch.from_numpy(br).to(dev)
     d_phi = torch.empty((w.nr, w.nt, w.np), dtype=torch.float64, device=dev)
     maxit = 500_000
+
+    if args.profile_kernels:
+        solver.solve_device(d_br, d_phi, 0.0, 8)
+        ms_p, ms_r = solver.time_kernels(args.kernel_reps)
+        src = torch.ones(w.n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_kernels": w.describe(), "update_p_ms": ms_p, "update_r_ms": ms_r,
+                          "copy_bytes_each_way": 8 * w.n, "launch": solver.stats()}), flush=True)
+        solver.close()
+        return
 
     for q in range(args.warmup):
         st, it, rr = solver.solve_device(d_br, d_phi, w.tol, maxit)
@@ -146,7 +170,7 @@ def main():
     traffic = load_traffic(w.name, dom)
     roofline = {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"stencil_march<{stats['tile_j']},{ {'update_p': 2, 'update_r': 3}[dom] },double>",
+                "kernel": kernel_name(stats, dom),
                 "alg_bytes_per_launch": kern[dom]["alg_bytes_per_launch"], "ms_per_launch": kern[dom]["ms"]}
 
     result = {
@@ -171,8 +195,7 @@ def main():
         "fp64_solve_s": round(elapsed / args.steps, 4),
         "kernels": {k: {"ms": round(v["ms"], 4), "gbs_alg": round(v["gbs"], 1)} for k, v in kern.items()},
         "loop_us_per_iter": round(loop_ms * 1e3 / max(1, total_iters), 2),
-        "launch": {"tile_j": stats["tile_j"], "chunk_i": stats["chunk_i"], "blocks": stats["blocks"],
-                   "pitch": stats["pitch"]},
+        "launch": {k: stats[k] for k in ("tile_p", "tile_r", "chunk_p", "chunk_r", "blocks_p", "blocks_r", "pitch")},
         "status": [pot3d.STATUS_NAMES.get(s, s) for s in statuses],
         "relres_true": stats["relres_true"],
         "phi_l2": phi_norm,

@@ -82,8 +82,11 @@ typedef struct pot3d_stats {
                                 (FP32 inner)                                               */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
-    int tile_j, chunk_i;     /* launch shape of the stencil kernels                         */
-    int blocks;              /* workgroups per stencil launch                               */
+    int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
+                                8/16/32 = workgroup tile of that many polar rows x 64
+                                cells; 102/104/108 = wavefront tile of 2/4/8 rows x 128   */
+    int chunk_p, chunk_r;    /* radial layers per workgroup chunk, per pass                 */
+    int blocks_p, blocks_r;  /* workgroups per launch, per pass                              */
 } pot3d_stats;
 
 /*
@@ -155,10 +158,18 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
  * Benchmark helper: launch the two per-iteration stencil kernels (the p
  * update with A p and p.Ap, then the r/x update with r.z and r.r) `reps` times
  * each, back to back on the context's stream, and report each kernel's
- * average duration in ms from hipEvents.  It runs on the vectors the context
- * holds and overwrites them; a later solve re-initializes everything.
+ * average duration in ms from hipEvents.  FP32-refined contexts time the FP32
+ * inner kernels.  It runs on the vectors the context holds and overwrites
+ * them; a later solve re-initializes everything.
  */
 int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
+
+/*
+ * FP32-refined contexts only: tolerance of each inner FP32 solve, relative to
+ * its right-hand side ||r||, in (0, 1) (default 1e-5), and the most outer
+ * defect-correction cycles (default 50).  POT3D_EINVAL otherwise.
+ */
+int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer);
 
 /* Free the context and all of its device memory.  NULL is a no-op. */
 void pot3d_destroy(pot3d_ctx *ctx);

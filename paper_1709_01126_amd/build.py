@@ -30,23 +30,33 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+LIB_CHECKED = os.path.join(PKG, "libpot3d_checked.so")
+
+
+def _build_one(lib: str, extra, tag: str, verbose: bool) -> str:
     objs = []
     os.makedirs(os.path.join(PKG, "_build"), exist_ok=True)
     for src in SOURCES:
-        obj = os.path.join(PKG, "_build", src.replace(".hip", ".o"))
-        cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(PKG, "_build", src.replace(".hip", f"{tag}.o"))
+        cmd = [HIPCC, *FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
+
+
+def build(verbose: bool = False) -> str:
+    """The production library, and a checked twin in which every global index of
+    the kernels is range-tested (used to try new kernels before the real one)."""
+    _build_one(LIB_CHECKED, ["-DPOT3D_CHECKED"], "_checked", verbose)
+    return _build_one(LIB, [], "", verbose)
 
 
 if __name__ == "__main__":

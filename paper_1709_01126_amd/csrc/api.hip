@@ -12,8 +12,14 @@
 // until the device sets its done flag, then recomputes the true residual and
 // the pole values (eq. (3)) and copies Phi out.  There is one host<->device
 // copy of each array per solve; the paper keeps its data resident the same
-// way (Sec. 3.1).  Inside the loop the host only polls a 64-byte status block
+// way (Sec. 3.1).  Inside the loop the host only polls a 128-byte status block
 // once per graph.
+//
+// FP32-refined contexts add FP32 copies of r, p (two buffers) and a correction
+// e, a second scalar block and a second graph whose kernels run in FP32 (dot
+// products still accumulate in FP64).  An outer loop in FP64 recomputes
+// r = b - A x, solves A e = r / ||r|| in FP32 to a looser inner tolerance, and
+// adds ||r|| e to x, until the FP64 residual meets tol.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,9 +55,11 @@ struct pot3d_ctx {
     int nr = 0, nt = 0, np = 0, pitch = 0;
     long long n = 0, npad = 0;
     int precision = POT3D_FP64;
-    int tj = 16, ci = 1;
+    int tile_p = kTileMarch8, tile_r = kTileWave2, tile_o = kTileWave2;
+    int max_blocks = 0;
+    int num_cu = 256;
     int graph_m = 16;
-    GridArgs grid{};
+    GridArgs grid_p{}, grid_r{}, grid_o{};   // update-p, update-r, other passes
 
     std::vector<double> rf, tf, pf;
     std::vector<RowCoef> rows_h;
@@ -68,6 +76,13 @@ struct pot3d_ctx {
     hipEvent_t ev_poll[2] = {nullptr, nullptr};
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_loop0 = nullptr, ev_loop1 = nullptr;
     hipGraphExec_t graph = nullptr;
+
+    // FP32-refined mode
+    float *r32 = nullptr, *p32[2] = {nullptr, nullptr}, *e32 = nullptr;
+    DevScalars *sc32 = nullptr;
+    hipGraphExec_t graph32 = nullptr;
+    double inner_tol = 1e-5;
+    int max_outer = 50;
 
     bool have_solution = false;
     pot3d_stats stats{};
@@ -136,7 +151,8 @@ int validate_grid(const double *rf, int nr, const double *tf, int nt, const doub
     if (upper_bc == POT3D_UPPER_CLOSED_WALL)
         return fail(nullptr, POT3D_EINVAL, "closed-wall upper boundary (singular system) is not supported");
     if (upper_bc != POT3D_UPPER_SOURCE_SURFACE) return fail(nullptr, POT3D_EINVAL, "unknown upper_bc");
-    if (precision != POT3D_FP64) return fail(nullptr, POT3D_EINVAL, "unsupported precision");
+    if (precision != POT3D_FP64 && precision != POT3D_FP32_REFINED)
+        return fail(nullptr, POT3D_EINVAL, "unsupported precision");
     return POT3D_OK;
 }
 
@@ -179,37 +195,100 @@ void build_tables(pot3d_ctx *c)
     for (int j = 0; j < nt; ++j) c->bfac_h[j] = std::sin(tc[j]) * dt[j] * rf[0] * rf[0];
 }
 
-// Workgroup shape: TJ polar rows x 64 azimuthal cells, radial chunks sized so
-// that one launch has about `target` workgroups.
-void choose_launch(pot3d_ctx *c)
+// Launch shape of one stencil pass.  `tile` picks the kernel:
+//   8/16/32 = workgroup tiles of that many polar rows x 64 cells (LDS plane);
+//   102/104/108 = wavefront tiles of 2/4/8 rows x 128 cells.
+// Radial chunks are sized so that one launch has about `target` workgroups.
+GridArgs make_grid(const pot3d_ctx *c, int tile, int target)
 {
-    int tj = env_int("POT3D_TJ", 16);
-    if (tj != 8 && tj != 16 && tj != 32) tj = 16;
-    const int target = std::max(1, env_int("POT3D_TARGET_BLOCKS", 2048));
-    const int ntj = (c->nt + tj - 1) / tj;
-    const int ntk = (c->np + kWave - 1) / kWave;
+    const int rows = tile_rows(tile), cols = tile_cols(tile);
+    const int ntj = (c->nt + rows - 1) / rows;
+    const int ntk = (c->np + cols - 1) / cols;
     const long long tiles = (long long)ntj * ntk;
+    // a wave tile is one wavefront; a workgroup holds four
+    const long long per_block = tile_is_wave(tile) ? kWaves : 1;
     int ci = env_int("POT3D_CI", 0);
     if (ci <= 0) {
-        long long want = (target + tiles - 1) / tiles;
+        // as many radial chunks as keep the launch within `target` workgroups
+        long long want = ((long long)target * per_block) / tiles;
         want = std::max<long long>(1, std::min<long long>(want, c->nr));
         ci = (int)((c->nr + want - 1) / want);
     }
     ci = std::max(1, std::min(ci, c->nr));
-    const int nchunk = (c->nr + ci - 1) / ci;
-    c->tj = tj;
-    c->ci = ci;
-    GridArgs &g = c->grid;
+    GridArgs g{};
     g.nr = c->nr;
     g.nt = c->nt;
     g.np = c->np;
     g.pitch = c->pitch;
     g.plane = (long long)c->nt * c->pitch;
     g.ci = ci;
-    g.nchunk = nchunk;
+    g.nchunk = (c->nr + ci - 1) / ci;
     g.ntj = ntj;
     g.ntk = ntk;
-    g.nblocks = (int)(tiles * nchunk);
+    g.nblocks = (int)((tiles * g.nchunk + per_block - 1) / per_block);
+    g.npad = c->npad;
+    return g;
+}
+
+int valid_tile(int tile, int dflt)
+{
+    switch (tile) {
+    case kTileMarch8: case kTileMarch16: case kTileMarch32: case kTileWave2: case kTileWave4: case kTileWave8:
+        return tile;
+    default:
+        return dflt;
+    }
+}
+
+// Workgroups that fit on the whole device at once for one kernel (for the
+// precision the context iterates in).  A launch sized to this runs as a single
+// wave of workgroups with no tail.
+int resident_blocks(const pot3d_ctx *c, int mode, int tile)
+{
+    const int per_cu = (c->precision == POT3D_FP32_REFINED) ? stencil_blocks_per_cu<float>(mode, tile)
+                                                            : stencil_blocks_per_cu<double>(mode, tile);
+    return std::max(1, per_cu) * std::max(1, c->num_cu);
+}
+
+// Default shapes (measured on MI355X at 151 x 301 x 601): both iteration
+// passes on the LDS-plane kernel, sized to one resident wave of workgroups.
+// POT3D_TILE[_P|_R] and POT3D_TARGET_BLOCKS[_P|_R] override.
+void choose_launch(pot3d_ctx *c)
+{
+    const int all = valid_tile(env_int("POT3D_TILE", 0), 0);
+    c->tile_p = valid_tile(env_int("POT3D_TILE_P", all ? all : kTileMarch8), kTileMarch8);
+    c->tile_r = valid_tile(env_int("POT3D_TILE_R", all ? all : kTileMarch8), kTileMarch8);
+    c->tile_o = all ? all : kTileWave2;
+    const int tb = env_int("POT3D_TARGET_BLOCKS", 0);
+    const int tp = env_int("POT3D_TARGET_BLOCKS_P", tb), tr = env_int("POT3D_TARGET_BLOCKS_R", tb);
+    c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : resident_blocks(c, kUpdateP, c->tile_p));
+    c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : resident_blocks(c, kUpdateR, c->tile_r));
+    c->grid_o = make_grid(c, c->tile_o, tb > 0 ? tb : 2048);
+    // The r/x update walks the tiles in the opposite order to the p update, so
+    // each pass starts on the tiles the previous pass touched last, while their
+    // lines may still sit in the 256 MB memory-side cache.
+    c->grid_p.reverse = env_int("POT3D_REVERSE_P", 0) != 0;
+    c->grid_r.reverse = env_int("POT3D_REVERSE_R", 1) != 0;
+    c->max_blocks = std::max(c->grid_p.nblocks, std::max(c->grid_r.nblocks, c->grid_o.nblocks));
+}
+
+void fill_shape(const pot3d_ctx *c, pot3d_stats &st)
+{
+    st.tile_p = c->tile_p;
+    st.tile_r = c->tile_r;
+    st.chunk_p = c->grid_p.ci;
+    st.chunk_r = c->grid_r.ci;
+    st.blocks_p = c->grid_p.nblocks;
+    st.blocks_r = c->grid_r.nblocks;
+}
+
+void set_tables(pot3d_ctx *c)
+{
+    for (GridArgs *g : {&c->grid_p, &c->grid_r, &c->grid_o}) {
+        g->rows = c->rows;
+        g->dphi = c->dphi;
+        g->ih = c->ih;
+    }
 }
 
 StencilVecs<double> base_vecs(pot3d_ctx *c)
@@ -220,27 +299,34 @@ StencilVecs<double> base_vecs(pot3d_ctx *c)
     return v;
 }
 
-int capture_graph(pot3d_ctx *c)
+// Capture m PCG iterations (update-p, alpha, update-r, beta/convergence) on the
+// idle context stream.  V is the vector type; the scalars stay FP64.
+template <typename V>
+int capture_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, DevScalars *sc, hipGraphExec_t *out)
 {
-    if (c->graph) return POT3D_OK;
     hipStream_t s = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
+    V *pb[2] = {p0, p1};
     for (int it = 0; it < c->graph_m && e == hipSuccess; ++it) {
-        StencilVecs<double> a = base_vecs(c);
-        a.in = c->r;
-        a.pold = c->p[it & 1];
-        a.pnew = c->p[(it + 1) & 1];
-        e = launch_stencil<double>(kUpdateP, c->tj, c->grid, a, s);
-        if (e == hipSuccess) e = launch_finish(kFinSigma, c->sc, c->partial, c->grid.nblocks, s);
+        StencilVecs<V> a{};
+        a.sc = sc;
+        a.partial = c->partial;
+        a.in = r;
+        a.pold = pb[it & 1];
+        a.pnew = pb[(it + 1) & 1];
+        e = launch_stencil<V>(kUpdateP, c->tile_p, c->grid_p, a, s);
+        if (e == hipSuccess) e = launch_finish(kFinSigma, sc, c->partial, c->grid_p.nblocks, s);
         if (e == hipSuccess) {
-            StencilVecs<double> bv = base_vecs(c);
-            bv.in = c->p[(it + 1) & 1];
-            bv.r = c->r;
-            bv.x = c->x;
-            e = launch_stencil<double>(kUpdateR, c->tj, c->grid, bv, s);
+            StencilVecs<V> bv{};
+            bv.sc = sc;
+            bv.partial = c->partial;
+            bv.in = pb[(it + 1) & 1];
+            bv.r = r;
+            bv.x = x;
+            e = launch_stencil<V>(kUpdateR, c->tile_r, c->grid_r, bv, s);
         }
-        if (e == hipSuccess) e = launch_finish(kFinRho, c->sc, c->partial, c->grid.nblocks, s);
+        if (e == hipSuccess) e = launch_finish(kFinRho, sc, c->partial, c->grid_r.nblocks, s);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &graph);
@@ -249,9 +335,38 @@ int capture_graph(pot3d_ctx *c)
         return fail(c, POT3D_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
     }
     if (e2 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
-    hipError_t e3 = hipGraphInstantiate(&c->graph, graph, nullptr, nullptr, 0);
+    hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return POT3D_OK;
+}
+
+// Replay `graph` until the scalar block `sc` reports done, keeping one graph
+// queued ahead of the poll.  Returns POT3D_OK or a HIP error status.
+int replay_until_done(pot3d_ctx *c, hipGraphExec_t graph, DevScalars *sc, hipStream_t s, int maxit, int *launches,
+                      DevScalars *final_out)
+{
+    int slot = 0;
+    int n = 0;
+    HIP_TRY(c, hipGraphLaunch(graph, s));
+    ++n;
+    HIP_TRY(c, hipMemcpyAsync(&c->h_sc[slot], sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipEventRecord(c->ev_poll[slot], s));
+    const long long max_launches = (long long)maxit / c->graph_m + 3;
+    for (;;) {
+        const int nxt = slot ^ 1;
+        HIP_TRY(c, hipGraphLaunch(graph, s));
+        ++n;
+        HIP_TRY(c, hipMemcpyAsync(&c->h_sc[nxt], sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipEventRecord(c->ev_poll[nxt], s));
+        HIP_TRY(c, hipEventSynchronize(c->ev_poll[slot]));
+        if (c->h_sc[slot].done || n > max_launches) break;
+        slot = nxt;
+    }
+    HIP_TRY(c, hipStreamSynchronize(s));
+    HIP_TRY(c, hipMemcpy(final_out, sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
+    *launches += n;
+    if (!final_out->done) return fail(c, POT3D_EDEVICE, "iteration loop ended without the device done flag");
     return POT3D_OK;
 }
 
@@ -260,11 +375,13 @@ void free_ctx(pot3d_ctx *c)
     if (!c) return;
     DeviceGuard guard(c->device);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
+    if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
     for (hipEvent_t *e : {&c->ev_poll[0], &c->ev_poll[1], &c->ev_t0, &c->ev_t1, &c->ev_loop0, &c->ev_loop1})
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->p[0], c->p[1],
-                    c->bplane, c->br, c->partial, c->poles, c->sc};
+                    c->bplane, c->br, c->partial, c->poles, c->sc,
+                    c->r32, c->p32[0], c->p32[1], c->e32, c->sc32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -295,6 +412,97 @@ int check_solve_args(pot3d_ctx *c, const void *br, const void *phi, double tol, 
     return POT3D_OK;
 }
 
+int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, DevScalars fin, int launches,
+                 int total_iters, int outer, double bytes_per_unknown, int *iters, double *relres_true);
+
+// FP64 Jacobi-PCG: r = b - A x0, first test, then graph replays until done.
+int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters,
+             double *relres_true)
+{
+    DevScalars init{};
+    init.tol = tol;
+    init.maxit = maxit;
+    c->h_sc[0] = init;
+    HIP_TRY(c, hipMemcpyAsync(c->sc, &c->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, launch_fill<double>(c->p[0], c->npad, 0.0, s));
+
+    StencilVecs<double> rv = base_vecs(c);
+    rv.in = c->x;
+    rv.r = c->r;
+    rv.bplane = c->bplane;
+    rv.store_r = 1;
+    rv.ignore_done = 1;
+    HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
+    HIP_TRY(c, launch_finish(kFinInit, c->sc, c->partial, c->grid_o.nblocks, s));
+
+    HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
+    int launches = 0;
+    DevScalars fin{};
+    int rc = replay_until_done(c, c->graph, c->sc, s, maxit, &launches, &fin);
+    if (rc != POT3D_OK) return rc;
+    HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
+    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, 64.0, iters, relres_true);
+}
+
+// FP32-refined: outer FP64 defect correction around FP32 Jacobi-PCG solves.
+//   repeat: r = b - A x (FP64); stop if ||r||/||b|| <= tol
+//           solve A e = r / ||r|| with FP32 PCG (FP64 dots) to inner_tol
+//           x += ||r|| e (FP64)
+// maxit caps the total number of inner iterations.
+int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit,
+                int *iters, double *relres_true)
+{
+    DevScalars init{};
+    init.tol = tol;
+    init.maxit = maxit;
+    c->h_sc[0] = init;
+    HIP_TRY(c, hipMemcpyAsync(c->sc, &c->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
+    int launches = 0, total = 0, outer = 0;
+    DevScalars out{};
+    const int nb_dots = std::max(1, std::min(c->max_blocks, c->nr * c->nt));
+    for (;;) {
+        StencilVecs<double> rv = base_vecs(c);
+        rv.in = c->x;
+        rv.r = c->r;
+        rv.bplane = c->bplane;
+        rv.store_r = 1;
+        rv.ignore_done = 1;
+        HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
+        HIP_TRY(c, launch_finish(kFinOuter, c->sc, c->partial, c->grid_o.nblocks, s));
+        HIP_TRY(c, hipMemcpyAsync(&c->h_sc[0], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        HIP_TRY(c, hipStreamSynchronize(s));
+        out = c->h_sc[0];
+        if (out.done) break;
+        if (outer >= c->max_outer || total >= maxit) {
+            out.status = POT3D_ENOCONV;
+            break;
+        }
+        HIP_TRY(c, launch_cast_residual(c->r, c->r32, c->e32, c->p32[0], c->npad, c->sc, s));
+        // Solve no further than the outer target needs: an inner reduction of
+        // tol / relres (with a factor 2 margin) already meets it.
+        DevScalars in{};
+        in.tol = std::max(c->inner_tol, 0.5 * tol / out.relres);
+        in.maxit = maxit - total;
+        c->h_sc[1] = in;
+        HIP_TRY(c, hipMemcpyAsync(c->sc32, &c->h_sc[1], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+        HIP_TRY(c, launch_dots_rz(c->grid_o, c->r32, c->partial, nb_dots, s));
+        HIP_TRY(c, launch_finish(kFinInner, c->sc32, c->partial, nb_dots, s));
+        DevScalars inner{};
+        int rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, &launches, &inner);
+        if (rc != POT3D_OK) return rc;
+        total += inner.k;
+        ++outer;
+        if (inner.status == POT3D_EBREAKDOWN) {
+            out.status = POT3D_EBREAKDOWN;
+            break;
+        }
+        HIP_TRY(c, launch_add_correction(c->x, c->e32, c->npad, c->sc, s));
+    }
+    HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
+    return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, 32.0, iters, relres_true);
+}
+
 // The solve proper.  br_dev: device Br (nt*np); phi0: initial guess or NULL
 // (host or device per `kind_in`); phi_out: destination (host or device).
 int run_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMemcpyKind kind_in, double *phi_out,
@@ -304,100 +512,124 @@ int run_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMemcpyK
     const size_t nrows = (size_t)c->nr * c->nt;
     c->have_solution = false;
     HIP_TRY(c, hipEventRecord(c->ev_t0, s));
-
     HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, c->bplane, s));
     if (phi0) HIP_TRY(c, copy_rows(c->x, pitchb, phi0, rowb, rowb, nrows, kind_in, s));
     else HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
-    HIP_TRY(c, launch_fill<double>(c->p[0], c->npad, 0.0, s));
+    if (c->precision == POT3D_FP32_REFINED) return run_refined(c, phi_out, kind_out, s, tol, maxit, iters, relres_true);
+    return run_fp64(c, phi_out, kind_out, s, tol, maxit, iters, relres_true);
+}
 
-    DevScalars init{};
-    init.tol = tol;
-    init.maxit = maxit;
-    c->h_sc[0] = init;
-    HIP_TRY(c, hipMemcpyAsync(c->sc, &c->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
-
-    // r = b - A x0 and the first residual test
-    StencilVecs<double> rv = base_vecs(c);
-    rv.in = c->x;
-    rv.r = c->r;
-    rv.bplane = c->bplane;
-    rv.store_r = 1;
-    rv.ignore_done = 1;
-    HIP_TRY(c, launch_stencil<double>(kResidual, c->tj, c->grid, rv, s));
-    HIP_TRY(c, launch_finish(kFinInit, c->sc, c->partial, c->grid.nblocks, s));
-
-    // Replay the m-iteration graph, keeping one graph queued ahead of the poll.
-    HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
-    int launches = 0;
-    int slot = 0;
-    HIP_TRY(c, hipGraphLaunch(c->graph, s));
-    ++launches;
-    HIP_TRY(c, hipMemcpyAsync(&c->h_sc[slot], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-    HIP_TRY(c, hipEventRecord(c->ev_poll[slot], s));
-    const long long max_launches = (long long)maxit / c->graph_m + 3;
-    for (;;) {
-        const int nxt = slot ^ 1;
-        HIP_TRY(c, hipGraphLaunch(c->graph, s));
-        ++launches;
-        HIP_TRY(c, hipMemcpyAsync(&c->h_sc[nxt], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipEventRecord(c->ev_poll[nxt], s));
-        HIP_TRY(c, hipEventSynchronize(c->ev_poll[slot]));
-        if (c->h_sc[slot].done || launches > max_launches) break;
-        slot = nxt;
-    }
-    HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-
-    // True residual ||b - A x|| (no store), pole values, Phi out.
+// Common tail: true residual (FP64), pole values, Phi out, statistics.
+int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, DevScalars fin, int launches,
+                 int total_iters, int outer, double bytes_per_unknown, int *iters, double *relres_true)
+{
+    const size_t rowb = (size_t)c->np * sizeof(double), pitchb = (size_t)c->pitch * sizeof(double);
+    const size_t nrows = (size_t)c->nr * c->nt;
     StencilVecs<double> tv = base_vecs(c);
     tv.in = c->x;
     tv.bplane = c->bplane;
     tv.store_r = 0;
     tv.ignore_done = 1;
-    HIP_TRY(c, hipStreamSynchronize(s));
-    DevScalars fin = c->h_sc[slot];
-    HIP_TRY(c, hipMemcpy(&fin, c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost));
-    if (!fin.done) return fail(c, POT3D_EDEVICE, "iteration loop ended without the device done flag");
     if (fin.zero_solution) HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
-    HIP_TRY(c, launch_stencil<double>(kResidual, c->tj, c->grid, tv, s));
-    HIP_TRY(c, launch_finish(kFinTrue, c->sc, c->partial, c->grid.nblocks, s));
+    HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, tv, s));
+    HIP_TRY(c, launch_finish(kFinTrue, c->sc, c->partial, c->grid_o.nblocks, s));
     HIP_TRY(c, launch_poles(c->x, c->dphi, c->nr, c->nt, c->np, c->pitch, kTwoPi, c->poles, s));
     HIP_TRY(c, copy_rows(phi_out, rowb, c->x, pitchb, rowb, nrows, kind_out, s));
     HIP_TRY(c, hipMemcpyAsync(&c->h_sc[0], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipEventRecord(c->ev_t1, s));
     HIP_TRY(c, hipStreamSynchronize(s));
-    fin = c->h_sc[0];
+    const double true_rel = c->h_sc[0].relres_true;
 
     float ms_total = 0.f, ms_loop = 0.f;
     (void)hipEventElapsedTime(&ms_total, c->ev_t0, c->ev_t1);
     (void)hipEventElapsedTime(&ms_loop, c->ev_loop0, c->ev_loop1);
     pot3d_stats &st = c->stats;
-    st.iters = fin.k;
-    st.outer = 1;
+    st.iters = total_iters;
+    st.outer = outer;
     st.status = fin.status;
     st.graph_launches = launches;
     st.relres = fin.relres;
-    st.relres_true = fin.zero_solution ? 0.0 : fin.relres_true;
+    st.relres_true = fin.zero_solution ? 0.0 : true_rel;
     st.solve_ms = ms_total;
     st.loop_ms = ms_loop;
-    st.bytes_per_iter = 64.0 * (double)c->n;
+    st.bytes_per_iter = bytes_per_unknown * (double)c->n;
     st.n = c->n;
     st.pitch = c->pitch;
-    st.tile_j = c->tj;
-    st.chunk_i = c->ci;
-    st.blocks = c->grid.nblocks;
+    fill_shape(c, st);
+    if (const unsigned line = take_oob_line(s))
+        return fail(c, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
     c->have_solution = true;
-    if (iters) *iters = fin.k;
+    if (iters) *iters = total_iters;
     if (relres_true) *relres_true = st.relres_true;
     if (fin.status == POT3D_EBREAKDOWN) return fail(c, POT3D_EBREAKDOWN, "breakdown: non-finite data or p.Ap <= 0");
     if (fin.status == POT3D_ENOCONV) return fail(c, POT3D_ENOCONV, "iteration cap reached before tol");
     return fin.status;
 }
 
+// Average launch time of the two iteration kernels, each launched `reps`
+// times back to back on the context stream (hipEvents), on the vectors held.
+template <typename V>
+int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_p, double *ms_r)
+{
+    hipStream_t s = ctx->stream;
+    DevScalars st{};
+    st.alpha = 1e-3;
+    st.beta = 0.5;
+    st.rho = 1.0;
+    st.bnorm = 1.0;
+    st.tol = 0.0;
+    st.maxit = 1 << 30;
+    ctx->h_sc[0] = st;
+    HIP_TRY(ctx, hipMemcpyAsync(sc, &ctx->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    StencilVecs<V> a{};
+    a.sc = sc;
+    a.partial = ctx->partial;
+    a.in = r;
+    a.pold = p0;
+    a.pnew = p1;
+    StencilVecs<V> bv{};
+    bv.sc = sc;
+    bv.partial = ctx->partial;
+    bv.in = p1;
+    bv.r = r;
+    bv.x = x;
+    HIP_TRY(ctx, launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s));   // warm-up
+    HIP_TRY(ctx, launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_t0, s));
+    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop0, s));
+    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop1, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    float ma = 0.f, mb = 0.f;
+    HIP_TRY(ctx, hipEventElapsedTime(&ma, ctx->ev_t0, ctx->ev_t1));
+    HIP_TRY(ctx, hipEventElapsedTime(&mb, ctx->ev_loop0, ctx->ev_loop1));
+    *ms_p = ma / reps;
+    *ms_r = mb / reps;
+    return POT3D_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-const char *pot3d_version(void) { return "pot3d-mi355x 0.1 (gfx950, FP64 Jacobi-PCG)"; }
+const char *pot3d_version(void)
+{
+    return checked_build() ? "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG, checked indices)"
+                           : "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG)";
+}
+
+int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (ctx->precision != POT3D_FP32_REFINED) return fail(ctx, POT3D_EINVAL, "context is not FP32-refined");
+    if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(ctx, POT3D_EINVAL, "inner_tol must be in (0, 1)");
+    if (max_outer < 1) return fail(ctx, POT3D_EINVAL, "max_outer must be >= 1");
+    ctx->inner_tol = inner_tol;
+    ctx->max_outer = max_outer;
+    return POT3D_OK;
+}
 
 const char *pot3d_last_error(const pot3d_ctx *ctx)
 {
@@ -423,7 +655,9 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
     c->nt = nt;
     c->np = np;
     c->precision = precision;
-    const int align = std::max(1, env_int("POT3D_PITCH_ALIGN", 8));
+    // rows padded to an even length at least, so two-cell (16-byte) accesses stay in the row
+    int align = std::max(2, env_int("POT3D_PITCH_ALIGN", 8));
+    align += align & 1;
     c->pitch = ((np + align - 1) / align) * align;
     c->n = (long long)nr * nt * np;
     c->npad = (long long)nr * nt * c->pitch;
@@ -433,6 +667,9 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
     c->tf.assign(t_faces, t_faces + nt + 1);
     c->pf.assign(p_faces, p_faces + np + 1);
     build_tables(c);
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
     choose_launch(c);
 
     auto bail = [&](hipError_t e, const char *what) {
@@ -463,7 +700,7 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
     CREATE_TRY(dalloc(&c->p[1], (size_t)c->npad));
     CREATE_TRY(dalloc(&c->bplane, (size_t)nt * c->pitch));
     CREATE_TRY(dalloc(&c->br, (size_t)nt * np));
-    CREATE_TRY(dalloc(&c->partial, (size_t)3 * c->grid.nblocks));
+    CREATE_TRY(dalloc(&c->partial, (size_t)3 * c->max_blocks));
     CREATE_TRY(dalloc(&c->poles, (size_t)2 * nr));
     CREATE_TRY(dalloc(&c->sc, 1));
     CREATE_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->h_sc), 2 * sizeof(DevScalars), hipHostMallocDefault));
@@ -476,12 +713,23 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
     CREATE_TRY(launch_fill<double>(c->poles, 2LL * nr, 0.0, c->stream));
     CREATE_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
     CREATE_TRY(hipStreamSynchronize(c->stream));
+    set_tables(c);
+    if (precision == POT3D_FP32_REFINED) {
+        CREATE_TRY(dalloc(&c->r32, (size_t)c->npad));
+        CREATE_TRY(dalloc(&c->p32[0], (size_t)c->npad));
+        CREATE_TRY(dalloc(&c->p32[1], (size_t)c->npad));
+        CREATE_TRY(dalloc(&c->e32, (size_t)c->npad));
+        CREATE_TRY(dalloc(&c->sc32, 1));
+        for (float *b : {c->r32, c->p32[0], c->p32[1], c->e32}) CREATE_TRY(launch_fill<float>(b, c->npad, 0.0f, c->stream));
+        CREATE_TRY(hipMemsetAsync(c->sc32, 0, sizeof(DevScalars), c->stream));
+        CREATE_TRY(hipStreamSynchronize(c->stream));
+    }
 #undef CREATE_TRY
-    c->grid.rows = c->rows;
-    c->grid.dphi = c->dphi;
-    c->grid.ih = c->ih;
-    // The iteration graph is captured once, on the idle context stream.
-    if (capture_graph(c) != POT3D_OK) {
+    // The iteration graphs are captured once, on the idle context stream.
+    int gc = capture_iterations<double>(c, c->r, c->p[0], c->p[1], c->x, c->sc, &c->graph);
+    if (gc == POT3D_OK && precision == POT3D_FP32_REFINED)
+        gc = capture_iterations<float>(c, c->r32, c->p32[0], c->p32[1], c->e32, c->sc32, &c->graph32);
+    if (gc != POT3D_OK) {
         std::string m = c->err;
         free_ctx(c);
         return fail(nullptr, POT3D_EDEVICE, m);
@@ -530,9 +778,11 @@ int pot3d_apply_device(pot3d_ctx *ctx, const double *d_x, double *d_y, void *str
     a.in = ctx->p[1];
     a.y = ctx->r;
     a.ignore_done = 1;
-    HIP_TRY(ctx, launch_stencil<double>(kApply, ctx->tj, ctx->grid, a, s));
+    HIP_TRY(ctx, launch_stencil<double>(kApply, ctx->tile_o, ctx->grid_o, a, s));
     HIP_TRY(ctx, copy_rows(d_y, rowb, ctx->r, pitchb, rowb, nrows, hipMemcpyDeviceToDevice, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (const unsigned line = take_oob_line(s))
+        return fail(ctx, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
     return POT3D_OK;
 }
 
@@ -572,10 +822,8 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     *out = ctx->stats;
     out->n = ctx->n;
     out->pitch = ctx->pitch;
-    out->tile_j = ctx->tj;
-    out->chunk_i = ctx->ci;
-    out->blocks = ctx->grid.nblocks;
-    out->bytes_per_iter = 64.0 * (double)ctx->n;
+    fill_shape(ctx, *out);
+    out->bytes_per_iter = (ctx->precision == POT3D_FP32_REFINED ? 32.0 : 64.0) * (double)ctx->n;
     return POT3D_OK;
 }
 
@@ -585,40 +833,17 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
     if (reps <= 0 || !ms_update_p || !ms_update_r) return fail(ctx, POT3D_EINVAL, "reps > 0 and outputs required");
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
-    hipStream_t s = ctx->stream;
-    DevScalars st{};
-    st.alpha = 1e-3;
-    st.beta = 0.5;
-    st.rho = 1.0;
-    st.bnorm = 1.0;
-    st.tol = 0.0;
-    st.maxit = 1 << 30;
-    ctx->h_sc[0] = st;
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->sc, &ctx->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
-    StencilVecs<double> a = base_vecs(ctx);
-    a.in = ctx->r;
-    a.pold = ctx->p[0];
-    a.pnew = ctx->p[1];
-    StencilVecs<double> bv = base_vecs(ctx);
-    bv.in = ctx->p[1];
-    bv.r = ctx->r;
-    bv.x = ctx->x;
-    HIP_TRY(ctx, launch_stencil<double>(kUpdateP, ctx->tj, ctx->grid, a, s));   // warm-up
-    HIP_TRY(ctx, launch_stencil<double>(kUpdateR, ctx->tj, ctx->grid, bv, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_t0, s));
-    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<double>(kUpdateP, ctx->tj, ctx->grid, a, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop0, s));
-    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<double>(kUpdateR, ctx->tj, ctx->grid, bv, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop1, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    float ma = 0.f, mb = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ma, ctx->ev_t0, ctx->ev_t1));
-    HIP_TRY(ctx, hipEventElapsedTime(&mb, ctx->ev_loop0, ctx->ev_loop1));
-    *ms_update_p = ma / reps;
-    *ms_update_r = mb / reps;
+    int rc;
+    if (ctx->precision == POT3D_FP32_REFINED)
+        rc = time_pair<float>(ctx, ctx->r32, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps, ms_update_p, ms_update_r);
+    else
+        rc = time_pair<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p, ms_update_r);
     ctx->have_solution = false;
-    return POT3D_OK;
+    if (rc == POT3D_OK) {
+        if (const unsigned line = take_oob_line(ctx->stream))
+            return fail(ctx, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
+    }
+    return rc;
 }
 
 void pot3d_destroy(pot3d_ctx *ctx) { free_ctx(ctx); }

@@ -25,9 +25,29 @@
 // that sums partials in a fixed order.
 #include "kernels.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pot3d {
+
+// Checked builds (-DPOT3D_CHECKED, libpot3d_checked.so) test every global
+// index of the stencil kernels against its array size.  An index out of range
+// is replaced by 0 and the source line is recorded in g_oob_line, which the
+// host reads after each solve.  Normal builds compile CHK(i, n) to i.
+#ifdef POT3D_CHECKED
+__device__ unsigned int g_oob_line = 0;
+__device__ __forceinline__ long long chk_index(long long i, long long n, unsigned line)
+{
+    if (i < 0 || i >= n) {
+        g_oob_line = line;
+        return 0;
+    }
+    return i;
+}
+#define CHK(i, n) chk_index((long long)(i), (long long)(n), __LINE__)
+#else
+#define CHK(i, n) (i)
+#endif
 
 template <typename V> __device__ __forceinline__ V vfma(V a, V b, V c);
 template <> __device__ __forceinline__ double vfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -42,7 +62,8 @@ __device__ __forceinline__ V diag_at(const RowCoef &rc, V dph, V ihm, V ihk)
 
 template <int TJ, int MODE, typename V>
 __global__ void __launch_bounds__(kThreads)
-stencil_march(GridArgs g, StencilVecs<V> v)
+stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
+              const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
 {
     static_assert(TJ % kWaves == 0 && 2 * TJ <= kWave, "tile rows");
     constexpr int M = TJ / kWaves;   // rows per wavefront
@@ -58,6 +79,7 @@ stencil_march(GridArgs g, StencilVecs<V> v)
     const int b = blockIdx.x;
     const int per = g.nblocks / kXcds;
     int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
+    if (g.reverse) L = g.nblocks - 1 - L;
     const int ic = L % g.nchunk;
     L /= g.nchunk;
     const int jt = L % g.ntj;
@@ -67,21 +89,20 @@ stencil_march(GridArgs g, StencilVecs<V> v)
     const int j0 = jt * TJ;
     const int k0 = kt * TK;
 
-    const int nt = g.nt, np = g.np;
+    const int nt = g.nt, np = g.np, nr = g.nr;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int k = k0 + lane;
     const bool kval = k < np;
+    const int kc = kval ? k : np - 1;          // in-row address for every lane
+    const V mk = kval ? V(1) : V(0);
     // LDS column of the k+1 neighbour: the last cell of a row wraps to k = 0,
     // which the right halo column holds.
     const int kp_col = (k == np - 1) ? TK + 1 : lane + 2;
 
-    V dph = 0, ihm = 0, ihk = 0;
-    if (kval) {
-        dph = (V)g.dphi[k];
-        ihm = (V)g.ih[k == 0 ? np - 1 : k - 1];
-        ihk = (V)g.ih[k];
-    }
+    const V dph = kval ? (V)g.dphi[CHK(kc, np)] : V(0);
+    const V ihm = kval ? (V)g.ih[CHK(kc == 0 ? np - 1 : kc - 1, np)] : V(0);
+    const V ihk = kval ? (V)g.ih[CHK(kc, np)] : V(0);
 
     // Halo ring of the tile in one layer: wave 0 the row below (j0-1), wave 1
     // the row above (j0+TJ), wave 2 the left and right columns (wrapped in phi).
@@ -91,7 +112,7 @@ stencil_march(GridArgs g, StencilVecs<V> v)
         hrow = (w == 0) ? 0 : TJ + 1;
         hcol = lane + 1;
         hj = (w == 0) ? j0 - 1 : j0 + TJ;
-        hk = k;
+        hk = kc;
         hval = kval && hj >= 0 && hj < nt;
     } else if (w == 2 && lane < 2 * TJ) {
         const bool left = lane < TJ;
@@ -101,108 +122,141 @@ stencil_march(GridArgs g, StencilVecs<V> v)
         hk = left ? (k0 == 0 ? np - 1 : k0 - 1) : (k0 + TK >= np ? 0 : k0 + TK);
         hval = hj < nt;
     }
+    const int hjc = min(max(hj, 0), nt - 1);   // clamped halo address
+    const V mh = hval ? V(1) : V(0);
     V hdph = 0, hihm = 0, hihk = 0;
-    if (MODE == kUpdateP && hval) {
-        hdph = (V)g.dphi[hk];
-        hihm = (V)g.ih[hk == 0 ? np - 1 : hk - 1];
-        hihk = (V)g.ih[hk];
+    if (MODE == kUpdateP) {
+        hdph = (V)g.dphi[CHK(hk, np)];
+        hihm = (V)g.ih[CHK(hk == 0 ? np - 1 : hk - 1, np)];
+        hihk = (V)g.ih[CHK(hk, np)];
     }
 
     V beta = 0, alpha = 0;
     if (MODE == kUpdateP) beta = (V)v.sc->beta;
     if (MODE == kUpdateR) alpha = (V)v.sc->alpha;
 
-    // Stencil operand at one point: the new search direction for update-p,
-    // the input vector otherwise.
-    auto operand = [&](int ip, int j, int kk, V pdph, V pihm, V pihk) -> V {
-        const long long idx = (long long)ip * g.plane + (long long)j * g.pitch + kk;
+    auto offs = [&](int ip, int j, int kk) -> long long {
+        return (long long)ip * g.plane + (long long)j * g.pitch + kk;
+    };
+    // Operand from raw loads: update-p forms z + beta p_old, otherwise the
+    // loaded value.  Masked by multiplication (clamped data are finite).
+    auto eval = [&](V a, V bold, const RowCoef &rc, V pdph, V pihm, V pihk, V mask) -> V {
         if constexpr (MODE == kUpdateP) {
-            const V d = diag_at<V>(g.rows[ip * nt + j], pdph, pihm, pihk);
-            return vfma<V>(beta, v.pold[idx], v.in[idx] / d);
+            const V d = diag_at<V>(rc, pdph + (V(1) - mask), pihm, pihk);
+            return vfma<V>(beta, bold, a / d) * mask;
         } else {
-            return v.in[idx];
+            return a * mask;
         }
     };
 
     V q0[M], q1[M], q2[M];
-    // Evaluate the operand on layer ip for the own points (into dst) and, if
-    // to_lds, on the tile plus halo ring into LDS slot `slot`.
-    auto produce = [&](int ip, int slot, V (&dst)[M], bool to_lds, bool store) {
+    // Layer ip: the own rows into dst (and LDS slot `slot` if to_lds, with the
+    // halo ring), storing the new direction when asked.  All loads first.
+    auto produce = [&](int ip_in, bool ip_on, int slot, V (&dst)[M], bool to_lds, bool store) {
+        const int ip = min(max(ip_in, 0), nr - 1);   // the layer below the first chunk is -1
+        V ra[M], rb[M];
+        RowCoef rcs[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int jc = min(j0 + w + kWaves * m, nt - 1);
+            const long long o = offs(ip, jc, kc);
+            ra[m] = vin[CHK(o, g.npad)];
+            if constexpr (MODE == kUpdateP) {
+                rb[m] = vpold[CHK(o, g.npad)];
+                rcs[m] = rows[CHK(ip * nt + jc, nr * nt)];
+            } else {
+                rb[m] = 0;
+            }
+        }
+        V ha = 0, hb = 0;
+        RowCoef hrc{};
+        if (to_lds) {
+            const long long o = offs(ip, hjc, hk);
+            ha = vin[CHK(o, g.npad)];
+            if constexpr (MODE == kUpdateP) {
+                hb = vpold[CHK(o, g.npad)];
+                hrc = rows[CHK(ip * nt + hjc, nr * nt)];
+            }
+        }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int row = w + kWaves * m;
             const int j = j0 + row;
-            V val = 0;
-            if (kval && j < nt) {
-                val = operand(ip, j, k, dph, ihm, ihk);
-                if constexpr (MODE == kUpdateP) {
-                    if (store) v.pnew[(long long)ip * g.plane + (long long)j * g.pitch + k] = val;
-                }
-            }
+            const V mrow = (ip_on && j < nt) ? mk : V(0);
+            const V val = eval(ra[m], rb[m], rcs[m], dph, ihm, ihk, mrow);
             dst[m] = val;
+            if constexpr (MODE == kUpdateP) {
+                if (store && kval && j < nt) vout[CHK(offs(ip, j, k), g.npad)] = val;
+            }
             if (to_lds) lds[slot][row + 1][lane + 1] = val;
         }
-        if (to_lds && hrow >= 0) lds[slot][hrow][hcol] = hval ? operand(ip, hj, hk, hdph, hihm, hihk) : V(0);
+        if (to_lds && hrow >= 0) lds[slot][hrow][hcol] = eval(ha, hb, hrc, hdph, hihm, hihk, ip_on ? mh : V(0));
     };
 
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
 
-    if (i0 > 0) {
-        produce(i0 - 1, 0, q0, false, false);
-    } else {
-#pragma unroll
-        for (int m = 0; m < M; ++m) q0[m] = 0;
-    }
-    produce(i0, i0 % 3, q1, true, MODE == kUpdateP);
+    produce(i0 - 1, i0 > 0, 0, q0, false, false);
+    produce(i0, true, i0 % 3, q1, true, MODE == kUpdateP);
 
     for (int i = i0; i < i1; ++i) {
-        if (i + 1 < g.nr) {
-            produce(i + 1, (i + 1) % 3, q2, true, MODE == kUpdateP && i + 1 < i1);
-        } else {
+        // this layer's r and x (update-r), issued with the next layer's operand
+        V rv[M], xv[M];
+        RowCoef rc[M];
 #pragma unroll
-            for (int m = 0; m < M; ++m) q2[m] = 0;
+        for (int m = 0; m < M; ++m) {
+            const int jc = min(j0 + w + kWaves * m, nt - 1);
+            rc[m] = rows[CHK(i * nt + jc, nr * nt)];
+            if constexpr (MODE == kUpdateR) {
+                const long long o = CHK(offs(i, jc, kc), g.npad);
+                rv[m] = vout[o];
+                xv[m] = vout2[o];
+            }
         }
+        produce(i + 1, i + 1 < nr, (i + 1) % 3, q2, true, MODE == kUpdateP && i + 1 < i1);
         __syncthreads();
         const int s = i % 3;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int row = w + kWaves * m;
             const int j = j0 + row;
-            if (kval && j < nt) {
-                const RowCoef &rc = g.rows[i * nt + j];
-                const V pc = q1[m];
-                const V pjm = lds[s][row][lane + 1];
-                const V pjp = lds[s][row + 2][lane + 1];
-                const V pkm = lds[s][row + 1][lane];
-                const V pkp = lds[s][row + 1][kp_col];
-                // (A p) = dphi_k (s pc - rm p_{i-1} - rp p_{i+1} - tm p_{j-1} - tp p_{j+1})
-                //       + pq (ih_{k-1} (pc - p_{k-1}) + ih_k (pc - p_{k+1}))
-                V t = (V)rc.s * pc;
-                t = vfma<V>(-(V)rc.rm, q0[m], t);
-                t = vfma<V>(-(V)rc.rp, q2[m], t);
-                t = vfma<V>(-(V)rc.tm, pjm, t);
-                t = vfma<V>(-(V)rc.tp, pjp, t);
-                V u = ihm * (pc - pkm);
-                u = vfma<V>(ihk, pc - pkp, u);
-                const V ap = vfma<V>(dph, t, (V)rc.pq * u);
-                const long long idx = (long long)i * g.plane + (long long)j * g.pitch + k;
-                if constexpr (MODE == kApply) {
-                    v.y[idx] = ap;
-                } else if constexpr (MODE == kResidual) {
-                    const double bval = (i == 0) ? v.bplane[(long long)j * g.pitch + k] : 0.0;
+            const bool on = kval && j < nt;
+            const RowCoef &r_ = rc[m];
+            const V pc = q1[m];
+            const V pjm = lds[s][row][lane + 1];
+            const V pjp = lds[s][row + 2][lane + 1];
+            const V pkm = lds[s][row + 1][lane];
+            const V pkp = lds[s][row + 1][kp_col];
+            // (A p) = dphi_k (s pc - rm p_{i-1} - rp p_{i+1} - tm p_{j-1} - tp p_{j+1})
+            //       + pq (ih_{k-1} (pc - p_{k-1}) + ih_k (pc - p_{k+1}))
+            V t = (V)r_.s * pc;
+            t = vfma<V>(-(V)r_.rm, q0[m], t);
+            t = vfma<V>(-(V)r_.rp, q2[m], t);
+            t = vfma<V>(-(V)r_.tm, pjm, t);
+            t = vfma<V>(-(V)r_.tp, pjp, t);
+            V u = ihm * (pc - pkm);
+            u = vfma<V>(ihk, pc - pkp, u);
+            const V ap = vfma<V>(dph, t, (V)r_.pq * u);
+            const long long idx = on ? CHK(offs(i, j, k), g.npad) : 0;
+            if constexpr (MODE == kApply) {
+                if (on) vout[idx] = ap;
+            } else if constexpr (MODE == kResidual) {
+                if (on) {
+                    const double bval = (i == 0) ? v.bplane[CHK((long long)j * g.pitch + k, (long long)nt * g.pitch)] : 0.0;
                     const V res = (V)(bval - (double)ap);
-                    if (v.store_r) v.r[idx] = res;
-                    const V z = res / diag_at<V>(rc, dph, ihm, ihk);
+                    if (v.store_r) vout[idx] = res;
+                    const V z = res / diag_at<V>(r_, dph, ihm, ihk);
                     acc0 += (double)res * (double)z;
                     acc1 += (double)res * (double)res;
                     acc2 += bval * bval;
-                } else if constexpr (MODE == kUpdateP) {
-                    acc0 += (double)pc * (double)ap;
-                } else {  // kUpdateR
-                    const V rn = vfma<V>(-alpha, ap, v.r[idx]);
-                    v.r[idx] = rn;
-                    v.x[idx] = vfma<V>(alpha, pc, v.x[idx]);
-                    const V z = rn / diag_at<V>(rc, dph, ihm, ihk);
+                }
+            } else if constexpr (MODE == kUpdateP) {
+                if (on) acc0 += (double)pc * (double)ap;
+            } else {  // kUpdateR
+                if (on) {
+                    const V rn = vfma<V>(-alpha, ap, rv[m]);
+                    vout[idx] = rn;
+                    vout2[idx] = vfma<V>(alpha, pc, xv[m]);
+                    const V z = rn / diag_at<V>(r_, dph, ihm, ihk);
                     acc0 += (double)rn * (double)z;
                     acc1 += (double)rn * (double)rn;
                 }
@@ -236,9 +290,335 @@ stencil_march(GridArgs g, StencilVecs<V> v)
                 s1 += red[q][1];
                 s2 += red[q][2];
             }
-            v.partial[b] = s0;
-            v.partial[g.nblocks + b] = s1;
-            v.partial[2 * g.nblocks + b] = s2;
+            v.partial[CHK(b, g.nblocks)] = s0;
+            v.partial[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
+            v.partial[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront-level marching kernel (no LDS, no barriers in the sweep).
+//
+// A task is one wavefront's column of the grid: M consecutive polar rows j0..j0+M-1
+// times a 128-cell azimuthal segment (two consecutive cells per lane, moved with
+// 16-byte accesses), over a chunk of radial layers.  The wavefront holds the
+// operand at layers i-1, i, i+1 of its own rows in registers.  Theta neighbours
+// are the neighbouring own rows; the two rows just outside the run are loaded
+// per layer.  Phi neighbours cross lanes with DPP wavefront shifts, and the
+// segment ends take the cells just outside it (wrapped in phi).
+//
+// The loads of a layer do not depend on each other and sit in one basic block:
+// out-of-range rows, layers and lanes read a clamped in-range address, and their
+// values are masked afterwards.  One layer therefore costs about one memory round
+// trip per wavefront, and the wavefronts never wait for each other until the
+// final reduction.
+// ---------------------------------------------------------------------------
+template <typename V> struct Pair;
+template <> struct Pair<double> { using T = double2; };
+template <> struct Pair<float> { using T = float2; };
+
+// Lane l receives the value of lane l-1 (lane 0 receives 0).
+__device__ __forceinline__ double lane_from_left(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Lane l receives the value of lane l+1 (lane 63 receives 0).
+__device__ __forceinline__ double lane_from_right(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_from_left(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_right(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+template <int M, int MODE, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
+             const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
+{
+    using P2 = typename Pair<V>::T;
+    constexpr int SEG = 2 * kWave;   // azimuthal cells per task
+    __shared__ double red[kWaves][3];
+
+    if (!v.ignore_done && v.sc->done) return;   // uniform over the workgroup
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int b = blockIdx.x;
+    const int per = g.nblocks / kXcds;
+    int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
+    if (g.reverse) L = g.nblocks - 1 - L;
+    const int task = L * kWaves + w;
+    const int ntask = g.ntj * g.ntk * g.nchunk;
+    const int nt = g.nt, np = g.np, nr = g.nr;
+
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+
+    if (task < ntask) {
+        const int jr = task % g.ntj;
+        const int rest = task / g.ntj;
+        const int ks = rest % g.ntk;
+        const int ic = rest / g.ntk;
+        const int i0 = ic * g.ci;
+        const int i1 = min(i0 + g.ci, nr);
+        const int j0 = jr * M;
+        const int k0 = ks * SEG;
+        const int kb = k0 + 2 * lane;            // this lane's first cell
+        const bool lane_on = kb < g.pitch;       // both cells inside the padded row
+        const int kc = lane_on ? kb : 0;         // in-row address for every lane
+        const bool v0 = kb < np, v1 = kb + 1 < np;
+        const int kl = (k0 == 0) ? np - 1 : k0 - 1;          // cell left of the segment
+        const int kr = (k0 + SEG >= np) ? 0 : k0 + SEG;      // cell right of the segment
+        const bool last0 = kb == np - 1, last1 = kb + 1 == np - 1;
+        const int jlo = max(j0 - 1, 0), jhi = min(j0 + M, nt - 1);       // clamped halo rows
+        const bool hlo_on = j0 > 0, hhi_on = j0 + M < nt;
+
+        const int kc0 = v0 ? kb : 0, kc1 = v1 ? kb + 1 : 0;
+        const V mv0 = v0 ? V(1) : V(0), mv1 = v1 ? V(1) : V(0);
+        const V dph0 = v0 ? (V)g.dphi[CHK(kc0, np)] : V(0), dph1 = v1 ? (V)g.dphi[CHK(kc1, np)] : V(0);
+        const V ihk0 = v0 ? (V)g.ih[CHK(kc0, np)] : V(0), ihk1 = v1 ? (V)g.ih[CHK(kc1, np)] : V(0);
+        const V ihm0 = v0 ? (V)g.ih[CHK(kc0 == 0 ? np - 1 : kc0 - 1, np)] : V(0), ihm1 = ihk0;
+        const V dphl = (V)g.dphi[CHK(kl, np)], ihml = (V)g.ih[CHK(kl == 0 ? np - 1 : kl - 1, np)], ihkl = (V)g.ih[CHK(kl, np)];
+        const V dphr = (V)g.dphi[CHK(kr, np)], ihmr = (V)g.ih[CHK(kr == 0 ? np - 1 : kr - 1, np)], ihkr = (V)g.ih[CHK(kr, np)];
+        const V beta = (MODE == kUpdateP) ? (V)v.sc->beta : V(0);
+        const V alpha = (MODE == kUpdateR) ? (V)v.sc->alpha : V(0);
+
+        auto rowoff = [&](int ip, int j) -> long long { return (long long)ip * g.plane + (long long)j * g.pitch; };
+        auto ld2 = [&](const V *p, long long off) -> P2 { return *reinterpret_cast<const P2 *>(p + CHK(off, g.npad - 1)); };
+
+        // Raw loads of the operand on a row segment, and their evaluation.
+        struct Raw { P2 a, b; };
+        auto raw_row = [&](int ip, int j) -> Raw {
+            const long long off = rowoff(ip, j) + kc;
+            Raw q;
+            q.a = ld2(vin, off);
+            if constexpr (MODE == kUpdateP) q.b = ld2(vpold, off);
+            return q;
+        };
+        // Evaluate a raw row segment with the row's coefficients (update-p: the
+        // new direction z + beta p_old; otherwise the loaded value), masked.
+        auto eval_row = [&](const Raw &q, const RowCoef &rc, bool on, V &a0, V &a1) {
+            V e0, e1;
+            if constexpr (MODE == kUpdateP) {
+                e0 = vfma<V>(beta, q.b.x, q.a.x / diag_at<V>(rc, dph0 + (V)(!v0), ihm0, ihk0));
+                e1 = vfma<V>(beta, q.b.y, q.a.y / diag_at<V>(rc, dph1 + (V)(!v1), ihm1, ihk1));
+            } else {
+                e0 = q.a.x;
+                e1 = q.a.y;
+            }
+            // masked by multiplication: a select would let the compiler sink the
+            // loads into a branch; clamped data are finite, so x * 0 = 0
+            const V mon = on ? V(1) : V(0);
+            a0 = e0 * (mon * mv0);
+            a1 = e1 * (mon * mv1);
+        };
+        // Raw loads of the operand at one cell (same address on every lane).
+        struct RawCell { V a, b; };
+        // (made wave-uniform so that the load is issued with the others, not
+        // sunk into the lanes that use it)
+        auto raw_cell = [&](int ip, int j, int kk) -> RawCell {
+            const long long off = rowoff(ip, j) + kk;
+            RawCell q;
+            q.a = wave_uniform(vin[CHK(off, g.npad)]);
+            if constexpr (MODE == kUpdateP) q.b = wave_uniform(vpold[CHK(off, g.npad)]);
+            else q.b = 0;
+            return q;
+        };
+        auto eval_cell = [&](const RawCell &q, const RowCoef &rc, V cdph, V cihm, V cihk) -> V {
+            if constexpr (MODE == kUpdateP) return vfma<V>(beta, q.b, q.a / diag_at<V>(rc, cdph, cihm, cihk));
+            else return q.a;
+        };
+        auto store2 = [&](V *dst, int ip, int j, V a0, V a1) {
+            P2 o;
+            o.x = v0 ? a0 : V(0);
+            o.y = v1 ? a1 : V(0);
+            if (lane_on) *reinterpret_cast<P2 *>(dst + CHK(rowoff(ip, j) + kc, g.npad - 1)) = o;
+        };
+
+        V q0[M][2], q1[M][2], q2[M][2];
+        // own rows of layer ip (clamped loads, masked values); store p if asked
+        auto produce_own = [&](int ip, bool ip_on, V (&dst)[M][2], bool store) {
+            const int ipc = min(ip, nr - 1);
+            Raw raw[M];
+            RowCoef rcs[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                raw[m] = raw_row(ipc, min(j0 + m, nt - 1));
+                if constexpr (MODE == kUpdateP) rcs[m] = rows[CHK(ipc * nt + min(j0 + m, nt - 1), nr * nt)];
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int j = j0 + m;
+                eval_row(raw[m], rcs[m], ip_on && j < nt, dst[m][0], dst[m][1]);
+                if constexpr (MODE == kUpdateP) {
+                    if (store && j < nt) store2(vout, ip, j, dst[m][0], dst[m][1]);
+                }
+            }
+        };
+
+        produce_own(i0 - 1 < 0 ? 0 : i0 - 1, i0 > 0, q0, false);
+        produce_own(i0, true, q1, MODE == kUpdateP);
+
+        for (int i = i0; i < i1; ++i) {
+            // ---- every load of this layer, unconditionally, from clamped addresses ----
+            const int ipn = min(i + 1, nr - 1);
+            Raw nxt[M], hraw[2];
+            RawCell cl[M], cr[M];
+            RowCoef rc[M], rcn[M], rch[2];
+            P2 rv[M], xv[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int jc = min(j0 + m, nt - 1);
+                rc[m] = rows[CHK(i * nt + jc, nr * nt)];
+                nxt[m] = raw_row(ipn, jc);
+                if constexpr (MODE == kUpdateP) rcn[m] = rows[CHK(ipn * nt + jc, nr * nt)];
+                cl[m] = raw_cell(i, jc, kl);
+                cr[m] = raw_cell(i, jc, kr);
+                if constexpr (MODE == kUpdateR) {
+                    rv[m] = ld2(vout, rowoff(i, jc) + kc);
+                    xv[m] = ld2(vout2, rowoff(i, jc) + kc);
+                }
+            }
+            hraw[0] = raw_row(i, jlo);
+            hraw[1] = raw_row(i, jhi);
+            if constexpr (MODE == kUpdateP) {
+                rch[0] = rows[CHK(i * nt + jlo, nr * nt)];
+                rch[1] = rows[CHK(i * nt + jhi, nr * nt)];
+            }
+            // ---- next layer's operand (stored as the new direction in update-p) ----
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int j = j0 + m;
+                eval_row(nxt[m], rcn[m], i + 1 < nr && j < nt, q2[m][0], q2[m][1]);
+                if constexpr (MODE == kUpdateP) {
+                    if (i + 1 < i1 && j < nt) store2(vout, i + 1, j, q2[m][0], q2[m][1]);
+                }
+            }
+            V hlo0, hlo1, hhi0, hhi1;
+            eval_row(hraw[0], rch[0], hlo_on, hlo0, hlo1);
+            eval_row(hraw[1], rch[1], hhi_on, hhi0, hhi1);
+            // ---- stencil on the own rows of layer i ----
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const int j = j0 + m;
+                const bool row_on = j < nt;          // uniform: rows past the pole are masked
+                const double wrow = row_on ? 1.0 : 0.0;
+                const V kL = eval_cell(cl[m], rc[m], dphl, ihml, ihkl);
+                const V kR = eval_cell(cr[m], rc[m], dphr, ihmr, ihkr);
+                const V c0 = q1[m][0], c1 = q1[m][1];
+                const V jm0 = (m > 0) ? q1[m - 1][0] : hlo0, jm1 = (m > 0) ? q1[m - 1][1] : hlo1;
+                const V jp0 = (m + 1 < M) ? q1[m + 1][0] : hhi0, jp1 = (m + 1 < M) ? q1[m + 1][1] : hhi1;
+                const V from_left = lane_from_left(c1);     // second cell of lane-1
+                const V from_right = lane_from_right(c0);   // first cell of lane+1
+                const V km0 = (lane == 0) ? kL : from_left;
+                const V kp0 = last0 ? kR : c1;
+                const V km1 = c0;
+                const V kp1 = (last1 || lane == kWave - 1) ? kR : from_right;
+                const V cc[2] = {c0, c1}, ii[2] = {q0[m][0], q0[m][1]}, ipv[2] = {q2[m][0], q2[m][1]};
+                const V jm[2] = {jm0, jm1}, jp[2] = {jp0, jp1}, km[2] = {km0, km1}, kp[2] = {kp0, kp1};
+                const V dph[2] = {dph0, dph1}, ihm[2] = {ihm0, ihm1}, ihk[2] = {ihk0, ihk1};
+                const bool ve[2] = {v0, v1};
+                const RowCoef &r_ = rc[m];
+                V ap[2];
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    V t = (V)r_.s * cc[e];
+                    t = vfma<V>(-(V)r_.rm, ii[e], t);
+                    t = vfma<V>(-(V)r_.rp, ipv[e], t);
+                    t = vfma<V>(-(V)r_.tm, jm[e], t);
+                    t = vfma<V>(-(V)r_.tp, jp[e], t);
+                    V u = ihm[e] * (cc[e] - km[e]);
+                    u = vfma<V>(ihk[e], cc[e] - kp[e], u);
+                    ap[e] = ve[e] ? vfma<V>(dph[e], t, (V)r_.pq * u) : V(0);
+                }
+                if constexpr (MODE == kApply) {
+                    if (row_on) store2(vout, i, j, ap[0], ap[1]);
+                } else if constexpr (MODE == kResidual) {
+                    V res[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        const double bval = (i == 0 && ve[e] && row_on) ? v.bplane[CHK((long long)min(j, nt - 1) * g.pitch + (e ? kc1 : kc0), (long long)nt * g.pitch)] : 0.0;
+                        res[e] = ve[e] ? (V)(bval - (double)ap[e]) : V(0);
+                        const V z = res[e] / diag_at<V>(r_, dph[e] + (V)(!ve[e]), ihm[e], ihk[e]);
+                        acc0 += wrow * ((double)res[e] * (double)z);
+                        acc1 += wrow * ((double)res[e] * (double)res[e]);
+                        acc2 += bval * bval;
+                    }
+                    if (v.store_r && row_on) store2(vout, i, j, res[0], res[1]);
+                } else if constexpr (MODE == kUpdateP) {
+                    acc0 += wrow * ((double)c0 * (double)ap[0] + (double)c1 * (double)ap[1]);
+                } else {  // kUpdateR
+                    const V rr[2] = {rv[m].x, rv[m].y}, xx[2] = {xv[m].x, xv[m].y};
+                    V rn[2], xn[2];
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        rn[e] = ve[e] ? vfma<V>(-alpha, ap[e], rr[e]) : V(0);
+                        xn[e] = ve[e] ? vfma<V>(alpha, cc[e], xx[e]) : V(0);
+                        const V z = rn[e] / diag_at<V>(r_, dph[e] + (V)(!ve[e]), ihm[e], ihk[e]);
+                        acc0 += wrow * ((double)rn[e] * (double)z);
+                        acc1 += wrow * ((double)rn[e] * (double)rn[e]);
+                    }
+                    if (row_on) {
+                        store2(vout, i, j, rn[0], rn[1]);
+                        store2(vout2, i, j, xn[0], xn[1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                q0[m][0] = q1[m][0];
+                q0[m][1] = q1[m][1];
+                q1[m][0] = q2[m][0];
+                q1[m][1] = q2[m][1];
+            }
+        }
+    }
+
+    if constexpr (MODE != kApply) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            acc0 += __shfl_xor(acc0, off, kWave);
+            acc1 += __shfl_xor(acc1, off, kWave);
+            acc2 += __shfl_xor(acc2, off, kWave);
+        }
+        if (lane == 0) {
+            red[w][0] = acc0;
+            red[w][1] = acc1;
+            red[w][2] = acc2;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) {
+                s0 += red[q][0];
+                s1 += red[q][1];
+                s2 += red[q][2];
+            }
+            v.partial[CHK(b, g.nblocks)] = s0;
+            v.partial[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
+            v.partial[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
     }
 }
@@ -270,9 +650,12 @@ __device__ __forceinline__ void block_sums(const double *partial, int nb, int nc
 __global__ void __launch_bounds__(kFinThreads)
 finish_kernel(int which, DevScalars *sc, const double *partial, int nb)
 {
-    if (which != kFinInit && which != kFinTrue && sc->done) return;
+    // the start-of-solve and end-of-solve finishers run whatever the done flag says
+    const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner;
+    if (!always && sc->done) return;
     double s[3] = {0.0, 0.0, 0.0};
-    block_sums(partial, nb, which == kFinSigma ? 1 : (which == kFinInit ? 3 : 2), s);
+    const int ncomp = (which == kFinSigma) ? 1 : ((which == kFinInit || which == kFinOuter) ? 3 : 2);
+    block_sums(partial, nb, ncomp, s);
     if (threadIdx.x != 0) return;
     if (which == kFinInit) {
         // After r = b - A x0: rho = r.z, ||b||, first residual check.
@@ -341,8 +724,110 @@ finish_kernel(int which, DevScalars *sc, const double *partial, int nb)
                 sc->done = 1;
             }
         }
-    } else {  // kFinTrue: ||b - A x|| / ||b|| from a residual pass with store_r = 0
+    } else if (which == kFinTrue) {  // ||b - A x|| / ||b|| from a residual pass with store_r = 0
         sc->relres_true = (sc->bnorm > 0.0) ? sqrt(s[1]) / sc->bnorm : 0.0;
+    } else if (which == kFinOuter) {
+        // Outer step of the refinement, after r = b - A x in FP64: test the true
+        // residual, and the scale that normalises the FP32 copy of r.
+        const double bnorm = sqrt(s[2]);
+        const double rnorm = sqrt(s[1]);
+        sc->bb = s[2];
+        sc->bnorm = bnorm;
+        sc->rr = s[1];
+        sc->zero_solution = 0;
+        sc->done = 0;
+        if (!isfinite(bnorm) || !isfinite(rnorm)) {
+            sc->relres = NAN;
+            sc->status = POT3D_EBREAKDOWN;
+            sc->done = 1;
+        } else if (bnorm == 0.0) {
+            sc->relres = 0.0;
+            sc->zero_solution = 1;
+            sc->status = POT3D_OK;
+            sc->done = 1;
+        } else {
+            sc->relres = rnorm / bnorm;
+            sc->relres_true = sc->relres;
+            sc->scale = 1.0 / rnorm;
+            if (sc->relres <= sc->tol) {
+                sc->status = POT3D_OK;
+                sc->done = 1;
+            } else {
+                sc->status = POT3D_ENOCONV;
+            }
+        }
+    } else {  // kFinInner: PCG start on the normalised FP32 residual (e = 0, r = r32)
+        const double rnorm = sqrt(s[1]);
+        sc->rho = s[0];
+        sc->rr = s[1];
+        sc->bb = s[1];
+        sc->bnorm = rnorm;
+        sc->alpha = 0.0;
+        sc->beta = 0.0;
+        sc->k = 0;
+        sc->zero_solution = 0;
+        sc->relres = 1.0;
+        sc->status = POT3D_ENOCONV;
+        sc->done = (!(rnorm > 0.0) || !isfinite(rnorm) || sc->maxit <= 0) ? 1 : 0;
+        if (!isfinite(rnorm)) sc->status = POT3D_EBREAKDOWN;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Refinement helpers (pointwise over the padded arrays; padding stays zero).
+// ---------------------------------------------------------------------------
+__global__ void cast_residual_kernel(const double *r64, float *r32, float *e32, float *p32, long long n,
+                                     const DevScalars *sc)
+{
+    const double scale = sc->scale;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        r32[q] = (float)(r64[q] * scale);
+        e32[q] = 0.0f;
+        p32[q] = 0.0f;
+    }
+}
+
+__global__ void add_correction_kernel(double *x64, const float *e32, long long n, const DevScalars *sc)
+{
+    const double inv = 1.0 / sc->scale;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x)
+        x64[q] = fma((double)e32[q], inv, x64[q]);
+}
+
+// r.z and r.r of an FP32 vector, one workgroup per group of (i, j) rows taken
+// in a fixed order, one partial per workgroup.
+__global__ void __launch_bounds__(256)
+dots_rz_kernel(GridArgs g, const float *r, double *partial, int nblocks)
+{
+    __shared__ double sh[2][256];
+    const int t = threadIdx.x;
+    double a0 = 0.0, a1 = 0.0;
+    const int nrows = g.nr * g.nt;
+    for (int row = blockIdx.x; row < nrows; row += nblocks) {
+        const RowCoef rc = g.rows[row];
+        const float *rp = r + (long long)row * g.pitch;
+        for (int k = t; k < g.np; k += 256) {
+            const float dph = (float)g.dphi[k], ihk = (float)g.ih[k];
+            const float ihm = (float)g.ih[k == 0 ? g.np - 1 : k - 1];
+            const float rv = rp[k];
+            const float z = rv / diag_at<float>(rc, dph, ihm, ihk);
+            a0 += (double)rv * (double)z;
+            a1 += (double)rv * (double)rv;
+        }
+    }
+    sh[0][t] = a0;
+    sh[1][t] = a1;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) {
+            sh[0][t] += sh[0][t + st];
+            sh[1][t] += sh[1][t + st];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        partial[blockIdx.x] = sh[0][0];
+        partial[nblocks + blockIdx.x] = sh[1][0];
     }
 }
 
@@ -397,30 +882,92 @@ pole_kernel(const double *x, const double *dphi, int nr, int nt, int np, int pit
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+// The vector a pass writes: y (apply), r (residual, update-r), p_new (update-p).
+// Passed to the kernels as restrict-qualified pointers with the inputs, so the
+// compiler may keep row coefficients in scalar registers and reorder loads.
+template <typename V>
+static V *out_vector(int mode, const StencilVecs<V> &v)
+{
+    return mode == kApply ? v.y : (mode == kUpdateP ? v.pnew : v.r);
+}
+
 template <int TJ, typename V>
 static hipError_t launch_tj(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
 {
     const dim3 grid(g.nblocks), block(kThreads);
+    V *out = out_vector(mode, v);
     switch (mode) {
-    case kApply: stencil_march<TJ, kApply, V><<<grid, block, 0, s>>>(g, v); break;
-    case kResidual: stencil_march<TJ, kResidual, V><<<grid, block, 0, s>>>(g, v); break;
-    case kUpdateP: stencil_march<TJ, kUpdateP, V><<<grid, block, 0, s>>>(g, v); break;
-    case kUpdateR: stencil_march<TJ, kUpdateR, V><<<grid, block, 0, s>>>(g, v); break;
+    case kApply: stencil_march<TJ, kApply, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kResidual: stencil_march<TJ, kResidual, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kUpdateP: stencil_march<TJ, kUpdateP, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kUpdateR: stencil_march<TJ, kUpdateR, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int M, typename V>
+static hipError_t launch_wave(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
+{
+    const dim3 grid(g.nblocks), block(kThreads);
+    V *out = out_vector(mode, v);
+    switch (mode) {
+    case kApply: stencil_wave<M, kApply, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kResidual: stencil_wave<M, kResidual, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kUpdateP: stencil_wave<M, kUpdateP, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kUpdateR: stencil_wave<M, kUpdateR, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename V>
-hipError_t launch_stencil(int mode, int tj, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
+hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
 {
-    switch (tj) {
-    case 8: return launch_tj<8, V>(mode, g, v, s);
-    case 16: return launch_tj<16, V>(mode, g, v, s);
-    case 32: return launch_tj<32, V>(mode, g, v, s);
+    switch (tile) {
+    case kTileMarch8: return launch_tj<8, V>(mode, g, v, s);
+    case kTileMarch16: return launch_tj<16, V>(mode, g, v, s);
+    case kTileMarch32: return launch_tj<32, V>(mode, g, v, s);
+    case kTileWave2: return launch_wave<2, V>(mode, g, v, s);
+    case kTileWave4: return launch_wave<4, V>(mode, g, v, s);
+    case kTileWave8: return launch_wave<8, V>(mode, g, v, s);
     default: return hipErrorInvalidValue;
     }
 }
+
+template <typename V>
+static const void *stencil_symbol(int mode, int tile)
+{
+#define POT3D_SYM(K, T)                                                                                 \
+    switch (mode) {                                                                                      \
+    case kApply: return reinterpret_cast<const void *>(&K<T, kApply, V>);                                \
+    case kResidual: return reinterpret_cast<const void *>(&K<T, kResidual, V>);                          \
+    case kUpdateP: return reinterpret_cast<const void *>(&K<T, kUpdateP, V>);                            \
+    case kUpdateR: return reinterpret_cast<const void *>(&K<T, kUpdateR, V>);                            \
+    default: return nullptr;                                                                             \
+    }
+    switch (tile) {
+    case kTileMarch8: POT3D_SYM(stencil_march, 8)
+    case kTileMarch16: POT3D_SYM(stencil_march, 16)
+    case kTileMarch32: POT3D_SYM(stencil_march, 32)
+    case kTileWave2: POT3D_SYM(stencil_wave, 2)
+    case kTileWave4: POT3D_SYM(stencil_wave, 4)
+    case kTileWave8: POT3D_SYM(stencil_wave, 8)
+    default: return nullptr;
+    }
+#undef POT3D_SYM
+}
+
+template <typename V>
+int stencil_blocks_per_cu(int mode, int tile)
+{
+    const void *f = stencil_symbol<V>(mode, tile);
+    int n = 0;
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) return 0;
+    return n;
+}
+template int stencil_blocks_per_cu<double>(int, int);
+template int stencil_blocks_per_cu<float>(int, int);
 
 template hipError_t launch_stencil<double>(int, int, const GridArgs &, const StencilVecs<double> &, hipStream_t);
 template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t);
@@ -450,6 +997,57 @@ hipError_t launch_fill(V *p, long long n, V val, hipStream_t s)
 }
 template hipError_t launch_fill<double>(double *, long long, double, hipStream_t);
 template hipError_t launch_fill<float>(float *, long long, float, hipStream_t);
+
+unsigned take_oob_line(hipStream_t s)
+{
+#ifdef POT3D_CHECKED
+    unsigned line = 0;
+    if (hipStreamSynchronize(s) != hipSuccess) return ~0u;
+    if (hipMemcpyFromSymbol(&line, HIP_SYMBOL(g_oob_line), sizeof(line)) != hipSuccess) return ~0u;
+    if (line) {
+        const unsigned zero = 0;
+        (void)hipMemcpyToSymbol(HIP_SYMBOL(g_oob_line), &zero, sizeof(zero));
+    }
+    return line;
+#else
+    (void)s;
+    return 0;
+#endif
+}
+
+bool checked_build()
+{
+#ifdef POT3D_CHECKED
+    return true;
+#else
+    return false;
+#endif
+}
+
+static unsigned stream_blocks(long long n)
+{
+    long long blocks = (n + 255) / 256;
+    return (unsigned)std::max<long long>(1, std::min<long long>(blocks, 8192));
+}
+
+hipError_t launch_cast_residual(const double *r64, float *r32, float *e32, float *p32, long long npad,
+                                const DevScalars *sc, hipStream_t s)
+{
+    cast_residual_kernel<<<stream_blocks(npad), 256, 0, s>>>(r64, r32, e32, p32, npad, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_correction(double *x64, const float *e32, long long npad, const DevScalars *sc, hipStream_t s)
+{
+    add_correction_kernel<<<stream_blocks(npad), 256, 0, s>>>(x64, e32, npad, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_dots_rz(const GridArgs &g, const float *r, double *partial, int nblocks, hipStream_t s)
+{
+    dots_rz_kernel<<<nblocks, 256, 0, s>>>(g, r, partial, nblocks);
+    return hipGetLastError();
+}
 
 hipError_t launch_poles(const double *x, const double *dphi, int nr, int nt, int np, int pitch, double period,
                         double *out, hipStream_t s)

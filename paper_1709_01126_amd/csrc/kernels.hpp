@@ -10,11 +10,32 @@ enum FinWhich : int {
     kFinInit = 0,   // after the initial residual pass: rho, ||b||, first test
     kFinSigma = 1,  // after update-p: alpha = rho / p.Ap
     kFinRho = 2,    // after update-r: convergence test, beta
-    kFinTrue = 3    // after a residual pass without store: true relative residual
+    kFinTrue = 3,   // after a residual pass without store: true relative residual
+    kFinOuter = 4,  // refinement, after the FP64 residual pass: outer test, scale = 1/||r||
+    kFinInner = 5   // refinement, after the r.z pass on the FP32 residual: inner start
 };
 
+// Stencil kernel shapes.  march: TJ x 64 tile per workgroup with an LDS plane;
+// wave: M rows x 128 cells per wavefront, registers and lane shuffles only.
+enum Tile : int {
+    kTileMarch8 = 8, kTileMarch16 = 16, kTileMarch32 = 32,
+    kTileWave2 = 102, kTileWave4 = 104, kTileWave8 = 108
+};
+inline bool tile_is_wave(int tile) { return tile > 100; }
+inline int tile_rows(int tile) { return tile > 100 ? tile - 100 : tile; }
+inline int tile_cols(int tile) { return tile > 100 ? 2 * kWave : kWave; }
+
 template <typename V>
-hipError_t launch_stencil(int mode, int tj, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s);
+hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s);
+
+// Workgroups of a stencil kernel that fit on one compute unit at once (0 if unknown).
+template <typename V>
+int stencil_blocks_per_cu(int mode, int tile);
+
+// Checked builds: the source line of the first out-of-range index seen since
+// the last call (0 if none), after waiting for stream s.  Normal builds: 0.
+unsigned take_oob_line(hipStream_t s);
+bool checked_build();
 
 hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s);
 
@@ -23,6 +44,15 @@ hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, 
 
 template <typename V>
 hipError_t launch_fill(V *p, long long n, V val, hipStream_t s);
+
+// Refinement helpers.
+// r32 = float(r64 * sc->scale); e32 = 0; p32 = 0 (all npad elements)
+hipError_t launch_cast_residual(const double *r64, float *r32, float *e32, float *p32, long long npad,
+                                const DevScalars *sc, hipStream_t s);
+// x64 += double(e32) / sc->scale (all npad elements)
+hipError_t launch_add_correction(double *x64, const float *e32, long long npad, const DevScalars *sc, hipStream_t s);
+// per-workgroup partials of r.z and r.r (z = D^-1 r) for an FP32 vector; nblocks <= cap
+hipError_t launch_dots_rz(const GridArgs &g, const float *r, double *partial, int nblocks, hipStream_t s);
 
 hipError_t launch_poles(const double *x, const double *dphi, int nr, int nt, int np, int pitch, double period,
                         double *out, hipStream_t s);

@@ -45,6 +45,7 @@ struct alignas(64) DevScalars {
     int status;        // POT3D_* status once done
     int zero_solution; // ||b|| = 0: the answer is Phi = 0
     int pad[3];
+    double scale;      // refinement: 1 / ||r64|| used to normalise the FP32 residual
 };
 
 // Launch geometry and tables common to every stencil launch.
@@ -54,6 +55,8 @@ struct GridArgs {
     int ci;               // radial layers per workgroup chunk
     int nchunk, ntj, ntk; // chunks along r, tiles along theta and phi
     int nblocks;
+    int reverse;
+    long long npad;       // elements of each vector (nr * nt * pitch), for checked builds          // 1: walk the tiles in reverse order (see choose_launch)
     const RowCoef *rows;  // nr * nt
     const double *dphi;   // np: phi_f[k+1] - phi_f[k]
     const double *ih;     // np: 1 / (phi_{k+1} - phi_k), wrapping at k = np-1

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpot3d.so")
+# POT3D_LIB=checked selects the build whose kernels range-test every index.
+LIB_PATH = os.path.join(_HERE, "libpot3d_checked.so" if os.environ.get("POT3D_LIB") == "checked" else "libpot3d.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 UPPER_SOURCE_SURFACE, UPPER_CLOSED_WALL = 0, 1
@@ -22,16 +23,17 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
                 EBREAKDOWN: "EBREAKDOWN"}
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
-            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_destroy", "pot3d_last_error",
-            "pot3d_version")
+            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement", "pot3d_destroy",
+            "pot3d_last_error", "pot3d_version")
 
 
 class pot3d_stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("outer", ctypes.c_int), ("status", ctypes.c_int),
                 ("graph_launches", ctypes.c_int), ("relres", ctypes.c_double), ("relres_true", ctypes.c_double),
                 ("solve_ms", ctypes.c_double), ("loop_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
-                ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_j", ctypes.c_int),
-                ("chunk_i", ctypes.c_int), ("blocks", ctypes.c_int)]
+                ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_p", ctypes.c_int),
+                ("tile_r", ctypes.c_int), ("chunk_p", ctypes.c_int), ("chunk_r", ctypes.c_int),
+                ("blocks_p", ctypes.c_int), ("blocks_r", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -68,6 +70,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_get_stats.restype = i
     lib.pot3d_time_kernels.argtypes = [vp, i, d, d]
     lib.pot3d_time_kernels.restype = i
+    lib.pot3d_set_refinement.argtypes = [vp, ctypes.c_double, i]
+    lib.pot3d_set_refinement.restype = i
     lib.pot3d_destroy.argtypes = [vp]
     lib.pot3d_destroy.restype = None
     lib.pot3d_last_error.argtypes = [vp]
@@ -160,6 +164,10 @@ def pot3d_time_kernels(ctx, reps):
     return st, a.value, b.value
 
 
+def pot3d_set_refinement(ctx, inner_tol, max_outer):
+    return load().pot3d_set_refinement(ctx, float(inner_tol), int(max_outer))
+
+
 def pot3d_destroy(ctx):
     if ctx:
         load().pot3d_destroy(ctx)
@@ -232,6 +240,9 @@ class Solver:
         st, a, b = pot3d_time_kernels(self.ctx, reps)
         self._check(st, (OK,))
         return a, b
+
+    def set_refinement(self, inner_tol, max_outer=50):
+        self._check(pot3d_set_refinement(self.ctx, inner_tol, max_outer), (OK,))
 
     def close(self):
         if self.ctx:

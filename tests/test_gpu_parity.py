@@ -230,9 +230,11 @@ def test_edge_cases():
         assert st7 == P.OK and np.array_equal(phi7, phi)
 
 
-@pytest.mark.parametrize("env", [{"POT3D_TJ": "8"}, {"POT3D_TJ": "32"}, {"POT3D_CI": "1"},
-                                 {"POT3D_CI": "1000"}, {"POT3D_PITCH_ALIGN": "1"},
-                                 {"POT3D_PITCH_ALIGN": "32", "POT3D_GRAPH_ITERS": "2"}])
+@pytest.mark.parametrize("env", [{"POT3D_TILE": "8"}, {"POT3D_TILE": "16"}, {"POT3D_TILE": "32"},
+                                 {"POT3D_TILE": "102"}, {"POT3D_TILE": "104"}, {"POT3D_TILE": "108"},
+                                 {"POT3D_CI": "1"}, {"POT3D_CI": "1000"}, {"POT3D_PITCH_ALIGN": "1"},
+                                 {"POT3D_PITCH_ALIGN": "32", "POT3D_GRAPH_ITERS": "2"},
+                                 {"POT3D_TILE": "16", "POT3D_CI": "3"}])
 def test_launch_shapes_agree(env, monkeypatch):
     for k, v in env.items():
         monkeypatch.setenv(k, v)

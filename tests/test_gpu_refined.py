@@ -1,0 +1,124 @@
+"""GPU: FP32-refined solves against the FP64 oracle.
+
+Refined mode runs FP32 PCG (FP32 vectors and stencil, FP64 dot accumulation)
+inside FP64 defect correction.  Its contract is the FP64 target residual.  The
+bar is that ||b - A Phi|| / ||b||, recomputed with the oracle's own operator,
+meets tol, and that Phi is as close to the oracle's FP64 Phi as two
+tol-accurate solutions are (<= 1e-7 relative here).  The error against the
+oracle is also printed per solve.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_01126_amd import pot3d as P
+from workloads import SMALL, WORKLOADS, magnetograms
+
+from test_gpu_parity import GRIDS, dev, label, make_faces
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def refined_solve(solver, br, tol, maxit, phi0=None):
+    d_phi = torch.empty(solver.shape, dtype=torch.float64, device="cuda:0")
+    st, it, rr = solver.solve_device(dev(br), d_phi, tol, maxit, phi0=None if phi0 is None else dev(phi0))
+    torch.cuda.synchronize()
+    return d_phi.cpu().numpy(), st, it, rr
+
+
+@pytest.mark.parametrize("case", [GRIDS[2], GRIDS[4], GRIDS[5], GRIDS[6]], ids=label)
+def test_refined_reaches_fp64_residual(case):
+    rf, tf, pf = make_faces(*case)
+    br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000)
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        phi, st, it, rr = refined_solve(s, br, tol, 200_000)
+        stats = s.stats()
+    tr = oracle.true_relres(ref["coef"], ref["b"], phi)
+    # rounding floor of computing ||b - A phi|| / ||b|| in FP64 (~64 ulps of |A||phi|)
+    floor = 64 * np.finfo(float).eps * np.linalg.norm(abs(oracle.to_sparse(ref["coef"])) @ np.abs(phi).ravel()) \
+        / np.linalg.norm(ref["b"])
+    e2 = np.linalg.norm(phi - ref["phi"]) / np.linalg.norm(ref["phi"])
+    emax = np.abs(phi - ref["phi"]).max() / np.abs(ref["phi"]).max()
+    print(f"[refined] {label(case)} inner iters={it} outer={stats['outer']} (fp64 oracle {ref['iters']}) "
+          f"true_relres={tr:.2e} err2={e2:.2e} errmax={emax:.2e}", flush=True)
+    assert st == P.OK and stats["outer"] >= 1
+    assert tr <= tol * 1.01
+    assert abs(rr - tr) <= 1e-3 * tr + floor, (rr, tr, floor)
+    assert e2 <= 1e-7 and emax <= 1e-7
+
+
+def test_refined_small_workload_and_poles():
+    rf, tf, pf = SMALL.faces()
+    br = SMALL.br((rf, tf, pf))
+    ref = oracle.solve(rf, tf, pf, br, SMALL.tol, 100_000)
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        phi, st, it, rr = refined_solve(s, br, SMALL.tol, 200_000)
+        north, south = s.pole_values()
+        stats = s.stats()
+        # host entry point: same answer bit for bit
+        phi_h, st_h, it_h, _ = s.solve(br, SMALL.tol, 200_000)
+    assert st == st_h == P.OK and it == it_h and np.array_equal(phi, phi_h)
+    assert oracle.true_relres(ref["coef"], ref["b"], phi) <= SMALL.tol * 1.01
+    no, so = oracle.pole_values(pf, ref["phi"])
+    np.testing.assert_allclose(north, no, rtol=0, atol=1e-7 * np.abs(ref["phi"]).max())
+    np.testing.assert_allclose(south, so, rtol=0, atol=1e-7 * np.abs(ref["phi"]).max())
+    assert stats["bytes_per_iter"] == 32.0 * SMALL.n
+
+
+def test_refined_edge_cases():
+    case = GRIDS[4]
+    rf, tf, pf = make_faces(*case)
+    nr, nt, np_ = case[:3]
+    br = magnetograms.br_bipoles(tf, pf, 30, seed=5)
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        phi, st, it, _ = refined_solve(s, np.zeros((nt, np_)), 1e-10, 100, phi0=np.ones((nr, nt, np_)))
+        assert st == P.OK and it == 0 and np.all(phi == 0)
+        phi, st, it, _ = refined_solve(s, br, 1e-10, 200_000)
+        assert st == P.OK and it > 10
+        phi2, st2, it2, _ = refined_solve(s, br, 1e-10, 200_000, phi0=phi)
+        assert st2 == P.OK and it2 == 0 and np.array_equal(phi, phi2)
+        _, st3, it3, rr3 = refined_solve(s, br, 1e-10, 5)
+        assert st3 == P.ENOCONV and it3 <= 5 and rr3 > 1e-10
+        bad = br.copy()
+        bad[2, 3] = np.inf
+        _, st4, it4, _ = refined_solve(s, bad, 1e-10, 100)
+        assert st4 == P.EBREAKDOWN and it4 == 0
+        # a looser inner tolerance takes more outer cycles to the same target
+        s.set_refinement(1e-3, 100)
+        phi5, st5, it5, rr5 = refined_solve(s, br, 1e-10, 200_000)
+        assert st5 == P.OK and rr5 <= 1e-10 and s.stats()["outer"] >= 3
+        with pytest.raises(P.Pot3dError):
+            s.set_refinement(0.0, 10)
+    with P.Solver(rf, tf, pf) as s64:
+        assert P.pot3d_set_refinement(s64.ctx, 1e-5, 10) == P.EINVAL
+
+
+def test_refined_full_size_bipole_151x301x601():
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_bipole_151x301x601.json")
+    if not os.path.exists(path):
+        pytest.skip("no oracle samples")
+    g = json.load(open(path))
+    w = WORKLOADS[g["workload"]]
+    rf, tf, pf = w.faces()
+    br = w.br((rf, tf, pf))
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        phi, st, it, rr = refined_solve(s, br, w.tol, 500_000)
+        stats = s.stats()
+    idx = np.array(g["indices"])
+    err = np.abs(phi.ravel()[idx] - np.array(g["phi"])).max() / g["phi_max_abs"]
+    coef = oracle.assemble(rf, tf, pf)
+    b = oracle.rhs(rf, tf, pf, br)
+    tr = oracle.true_relres(coef, b, phi)
+    print(f"[refined full size] inner iters={it} outer={stats['outer']} (fp64 oracle {g['iters']}) "
+          f"true_relres={tr:.3e} sampled max rel err vs FP64 oracle={err:.2e} solve_ms={stats['solve_ms']:.0f}",
+          flush=True)
+    assert st == P.OK
+    assert tr <= w.tol * 1.01
+    assert err <= 1e-7
