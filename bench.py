@@ -58,6 +58,54 @@ def load_traffic(workload: str, kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
+    """HBM bytes per launch of the two iteration kernels from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the device copy of N doubles in the same run (known bytes / counter)."""
+    import csv
+    import glob
+    import statistics
+
+    from workloads import WORKLOADS
+
+    n = WORKLOADS[workload].n
+
+    def per_kernel(folder, counter):
+        path = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)[0]
+        out = {}
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] == counter:
+                out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]) * 1024.0)
+        return out
+
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    copy_fetch = fetch["__amd_rocclr_copyBuffer"][-1]
+    copy_write = write["__amd_rocclr_copyBuffer"][-1]
+    f_scale = 8.0 * n / copy_fetch
+    w_scale = 8.0 * n / copy_write
+    kernels = {}
+    for key, mode in (("update_p", ", 2, double>"), ("update_r", ", 3, double>")):
+        name = [k for k in fetch if "stencil_" in k and mode in k][0]
+        # dispatches that ran (the graph's launches after convergence return at once)
+        real_f = [x for x in fetch[name] if x > 0.1 * max(fetch[name])]
+        real_w = [x for x in write[name] if x > 0.1 * max(write[name])]
+        fb = statistics.median(real_f) * f_scale
+        wb = statistics.median(real_w) * w_scale
+        alg = (24.0 if key == "update_p" else 40.0) * n
+        kernels[key] = {"kernel": name.split("(")[0], "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                        "hbm_bytes_per_launch": fb + wb, "alg_bytes_per_launch": alg,
+                        "traffic_over_alg": (fb + wb) / alg}
+    out = {"workload": workload, "kernel_source_hash": kernel_source_hash(),
+           "calibration": {"copy_bytes": 8.0 * n, "fetch_counter_bytes": copy_fetch, "write_counter_bytes": copy_write,
+                           "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": kernels}
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def kernel_name(stats, which):
     tile = stats["tile_p"] if which == "update_p" else stats["tile_r"]
     mode = 2 if which == "update_p" else 3
@@ -96,10 +144,16 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) of a --profile-kernels "
+                         "run into profiles/traffic_<workload>.json and exit")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short run for hardware counters: a few iterations, the two stencil kernels "
                          "--kernel-reps times each, and one device copy of N doubles (counter calibration)")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.workload, *args.summarize_pmc)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this solver runs on a single device (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
@@ -125,10 +179,15 @@ def main():
     if args.profile_kernels:
         solver.solve_device(d_br, d_phi, 0.0, 8)
         ms_p, ms_r = solver.time_kernels(args.kernel_reps)
+        # counter calibration: a device copy of N doubles whose source is not in
+        # the 256 MB memory-side cache (a 1 GB fill runs in between)
         src = torch.ones(w.n, dtype=torch.float64, device=dev)
+        flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        flush.fill_(2.0)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        del flush
         print(json.dumps({"profile_kernels": w.describe(), "update_p_ms": ms_p, "update_r_ms": ms_r,
                           "copy_bytes_each_way": 8 * w.n, "launch": solver.stats()}), flush=True)
         solver.close()

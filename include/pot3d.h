@@ -156,9 +156,10 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
 
 /*
  * Benchmark helper: launch the two per-iteration stencil kernels (the p
- * update with A p and p.Ap, then the r/x update with r.z and r.r) `reps` times
- * each, back to back on the context's stream, and report each kernel's
- * average duration in ms from hipEvents.  FP32-refined contexts time the FP32
+ * update with A p and p.Ap, then the r/x update with r.z and r.r) alternately,
+ * `reps` times each, on the context's stream as in the iteration, and report
+ * each kernel's average duration in ms from hipEvents recorded between the
+ * launches.  FP32-refined contexts time the FP32
  * inner kernels.  It runs on the vectors the context holds and overwrites
  * them; a later solve re-initializes everything.
  */

@@ -251,7 +251,9 @@ int resident_blocks(const pot3d_ctx *c, int mode, int tile)
 }
 
 // Default shapes (measured on MI355X at 151 x 301 x 601): both iteration
-// passes on the LDS-plane kernel, sized to one resident wave of workgroups.
+// passes on the LDS-plane kernel, with radial chunks sized so one launch fills
+// at most half of the resident workgroup slots: fewer, longer chunks repeat
+// fewer boundary layers, and a single wave of workgroups leaves no tail.
 // POT3D_TILE[_P|_R] and POT3D_TARGET_BLOCKS[_P|_R] override.
 void choose_launch(pot3d_ctx *c)
 {
@@ -261,8 +263,8 @@ void choose_launch(pot3d_ctx *c)
     c->tile_o = all ? all : kTileWave2;
     const int tb = env_int("POT3D_TARGET_BLOCKS", 0);
     const int tp = env_int("POT3D_TARGET_BLOCKS_P", tb), tr = env_int("POT3D_TARGET_BLOCKS_R", tb);
-    c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : resident_blocks(c, kUpdateP, c->tile_p));
-    c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : resident_blocks(c, kUpdateR, c->tile_r));
+    c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : resident_blocks(c, kUpdateP, c->tile_p) / 2);
+    c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : resident_blocks(c, kUpdateR, c->tile_r) / 2);
     c->grid_o = make_grid(c, c->tile_o, tb > 0 ? tb : 2048);
     // The r/x update walks the tiles in the opposite order to the p update, so
     // each pass starts on the tiles the previous pass touched last, while their
@@ -566,8 +568,10 @@ int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStrea
     return fin.status;
 }
 
-// Average launch time of the two iteration kernels, each launched `reps`
-// times back to back on the context stream (hipEvents), on the vectors held.
+// Average duration of the two iteration kernels, launched alternately
+// (update-p, update-r) `reps` times on the context stream as in the iteration.
+// Each launch carries start/stop events stamped by the dispatch itself.  Runs
+// on the vectors the context holds.
 template <typename V>
 int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_p, double *ms_r)
 {
@@ -587,27 +591,43 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
     a.in = r;
     a.pold = p0;
     a.pnew = p1;
+    a.ignore_done = 1;
     StencilVecs<V> bv{};
     bv.sc = sc;
     bv.partial = ctx->partial;
     bv.in = p1;
     bv.r = r;
     bv.x = x;
-    HIP_TRY(ctx, launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s));   // warm-up
-    HIP_TRY(ctx, launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_t0, s));
-    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_t1, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop0, s));
-    for (int q = 0; q < reps; ++q) HIP_TRY(ctx, launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s));
-    HIP_TRY(ctx, hipEventRecord(ctx->ev_loop1, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    float ma = 0.f, mb = 0.f;
-    HIP_TRY(ctx, hipEventElapsedTime(&ma, ctx->ev_t0, ctx->ev_t1));
-    HIP_TRY(ctx, hipEventElapsedTime(&mb, ctx->ev_loop0, ctx->ev_loop1));
-    *ms_p = ma / reps;
-    *ms_r = mb / reps;
-    return POT3D_OK;
+    bv.ignore_done = 1;
+    std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
+    for (auto &e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            for (auto &f : ev)
+                if (f) (void)hipEventDestroy(f);
+            return fail(ctx, POT3D_EDEVICE, "hipEventCreate failed");
+        }
+    }
+    int rc = POT3D_OK;
+    hipError_t e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s);   // warm-up
+    if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s);
+    for (int q = 0; q < reps && e == hipSuccess; ++q) {
+        e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s, ev[4 * q], ev[4 * q + 1]);
+        if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s, ev[4 * q + 2], ev[4 * q + 3]);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    double sp = 0.0, sr = 0.0;
+    for (int q = 0; q < reps && e == hipSuccess; ++q) {
+        float t1 = 0.f, t2 = 0.f;
+        e = hipEventElapsedTime(&t1, ev[4 * q], ev[4 * q + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[4 * q + 2], ev[4 * q + 3]);
+        sp += t1;
+        sr += t2;
+    }
+    for (auto &f : ev) (void)hipEventDestroy(f);
+    if (e != hipSuccess) rc = fail(ctx, POT3D_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
+    *ms_p = sp / reps;
+    *ms_r = sr / reps;
+    return rc;
 }
 
 }  // namespace

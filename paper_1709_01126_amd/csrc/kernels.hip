@@ -25,6 +25,8 @@
 // that sums partials in a fixed order.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -75,15 +77,17 @@ stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, co
 
     // Workgroup -> tile.  Hardware hands consecutive workgroup ids to the 8
     // XCDs in turn; renumber so that each XCD works on a contiguous range of
-    // logical tiles (radial chunk fastest) and shares their halos in its L2.
+    // logical tiles and shares their halos in its L2.  The phi tile varies
+    // fastest: the phi-halo cells of a tile sit in 128-byte lines owned by its
+    // phi neighbours, which then run beside it on the same XCD.
     const int b = blockIdx.x;
     const int per = g.nblocks / kXcds;
     int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
     if (g.reverse) L = g.nblocks - 1 - L;
+    const int kt = L % g.ntk;
+    L /= g.ntk;
     const int ic = L % g.nchunk;
-    L /= g.nchunk;
-    const int jt = L % g.ntj;
-    const int kt = L / g.ntj;
+    const int jt = L / g.nchunk;
     const int i0 = ic * g.ci;
     const int i1 = min(i0 + g.ci, g.nr);
     const int j0 = jt * TJ;
@@ -376,10 +380,10 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
 
     if (task < ntask) {
-        const int jr = task % g.ntj;
-        const int rest = task / g.ntj;
-        const int ks = rest % g.ntk;
-        const int ic = rest / g.ntk;
+        const int ks = task % g.ntk;
+        const int rest = task / g.ntk;
+        const int jr = rest % g.ntj;
+        const int ic = rest / g.ntj;
         const int i0 = ic * g.ci;
         const int i1 = min(i0 + g.ci, nr);
         const int j0 = jr * M;
@@ -891,46 +895,59 @@ static V *out_vector(int mode, const StencilVecs<V> &v)
     return mode == kApply ? v.y : (mode == kUpdateP ? v.pnew : v.r);
 }
 
-template <int TJ, typename V>
-static hipError_t launch_tj(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
+// Launch one stencil kernel; with events, through hipExtLaunchKernelGGL so
+// that the events carry the dispatch's own start and end timestamps.
+template <typename K, typename V>
+static hipError_t launch_kernel(K kern, const GridArgs &g, const StencilVecs<V> &v, V *out, hipStream_t s,
+                                hipEvent_t e0, hipEvent_t e1)
 {
     const dim3 grid(g.nblocks), block(kThreads);
+    if (e0 || e1)
+        hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, g, v, g.rows, v.in, v.pold, out, v.x);
+    else
+        hipLaunchKernelGGL(kern, grid, block, 0, s, g, v, g.rows, v.in, v.pold, out, v.x);
+    return hipGetLastError();
+}
+
+template <int TJ, typename V>
+static hipError_t launch_tj(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s, hipEvent_t e0,
+                            hipEvent_t e1)
+{
     V *out = out_vector(mode, v);
     switch (mode) {
-    case kApply: stencil_march<TJ, kApply, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kResidual: stencil_march<TJ, kResidual, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kUpdateP: stencil_march<TJ, kUpdateP, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kUpdateR: stencil_march<TJ, kUpdateR, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kApply: return launch_kernel(stencil_march<TJ, kApply, V>, g, v, out, s, e0, e1);
+    case kResidual: return launch_kernel(stencil_march<TJ, kResidual, V>, g, v, out, s, e0, e1);
+    case kUpdateP: return launch_kernel(stencil_march<TJ, kUpdateP, V>, g, v, out, s, e0, e1);
+    case kUpdateR: return launch_kernel(stencil_march<TJ, kUpdateR, V>, g, v, out, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int M, typename V>
-static hipError_t launch_wave(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
+static hipError_t launch_wave(int mode, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s, hipEvent_t e0,
+                              hipEvent_t e1)
 {
-    const dim3 grid(g.nblocks), block(kThreads);
     V *out = out_vector(mode, v);
     switch (mode) {
-    case kApply: stencil_wave<M, kApply, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kResidual: stencil_wave<M, kResidual, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kUpdateP: stencil_wave<M, kUpdateP, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
-    case kUpdateR: stencil_wave<M, kUpdateR, V><<<grid, block, 0, s>>>(g, v, g.rows, v.in, v.pold, out, v.x); break;
+    case kApply: return launch_kernel(stencil_wave<M, kApply, V>, g, v, out, s, e0, e1);
+    case kResidual: return launch_kernel(stencil_wave<M, kResidual, V>, g, v, out, s, e0, e1);
+    case kUpdateP: return launch_kernel(stencil_wave<M, kUpdateP, V>, g, v, out, s, e0, e1);
+    case kUpdateR: return launch_kernel(stencil_wave<M, kUpdateR, V>, g, v, out, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <typename V>
-hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s)
+hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s, hipEvent_t e0,
+                          hipEvent_t e1)
 {
     switch (tile) {
-    case kTileMarch8: return launch_tj<8, V>(mode, g, v, s);
-    case kTileMarch16: return launch_tj<16, V>(mode, g, v, s);
-    case kTileMarch32: return launch_tj<32, V>(mode, g, v, s);
-    case kTileWave2: return launch_wave<2, V>(mode, g, v, s);
-    case kTileWave4: return launch_wave<4, V>(mode, g, v, s);
-    case kTileWave8: return launch_wave<8, V>(mode, g, v, s);
+    case kTileMarch8: return launch_tj<8, V>(mode, g, v, s, e0, e1);
+    case kTileMarch16: return launch_tj<16, V>(mode, g, v, s, e0, e1);
+    case kTileMarch32: return launch_tj<32, V>(mode, g, v, s, e0, e1);
+    case kTileWave2: return launch_wave<2, V>(mode, g, v, s, e0, e1);
+    case kTileWave4: return launch_wave<4, V>(mode, g, v, s, e0, e1);
+    case kTileWave8: return launch_wave<8, V>(mode, g, v, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -969,8 +986,10 @@ int stencil_blocks_per_cu(int mode, int tile)
 template int stencil_blocks_per_cu<double>(int, int);
 template int stencil_blocks_per_cu<float>(int, int);
 
-template hipError_t launch_stencil<double>(int, int, const GridArgs &, const StencilVecs<double> &, hipStream_t);
-template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t);
+template hipError_t launch_stencil<double>(int, int, const GridArgs &, const StencilVecs<double> &, hipStream_t,
+                                          hipEvent_t, hipEvent_t);
+template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t,
+                                         hipEvent_t, hipEvent_t);
 
 hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s)
 {

@@ -25,8 +25,10 @@ inline bool tile_is_wave(int tile) { return tile > 100; }
 inline int tile_rows(int tile) { return tile > 100 ? tile - 100 : tile; }
 inline int tile_cols(int tile) { return tile > 100 ? 2 * kWave : kWave; }
 
+// e0/e1 (optional): events stamped with the kernel's own start and end.
 template <typename V>
-hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s);
+hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVecs<V> &v, hipStream_t s,
+                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // Workgroups of a stencil kernel that fit on one compute unit at once (0 if unknown).
 template <typename V>

@@ -39,7 +39,7 @@ def sample_indices(nr, nt, np_, count=1024, seed=2024):
     return np.array(sorted(idx), dtype=np.int64)
 
 
-def main(name):
+def main(name, solve=True):
     w = WORKLOADS[name]
     rf, tf, pf = w.faces()
     br = w.br((rf, tf, pf))
@@ -52,6 +52,17 @@ def main(name):
         xk, itk, rrk, stk = oracle.pcg(coef, b, 0.0, K)
         fixed[str(K)] = {"relres": rrk, "phi": xk.ravel()[idx].tolist(), "phi_max_abs": float(np.abs(xk).max())}
     t1 = time.time()
+    if not solve:
+        # fixed-count samples only (a full oracle solve at this size takes hours)
+        out = {"_source": "oracle/pot3d_oracle.c Jacobi-PCG on the named seeded workload, fixed-count iterates only; "
+                          "written by tests/golden/make_oracle_samples.py (calls only oracle/ and workloads/)",
+               "workload": name, "nr": w.nr, "nt": w.nt, "np": w.np, "tol": w.tol,
+               "indices": idx.tolist(), "fixed": fixed, "oracle_seconds": {"fixed_k": t1 - t0}}
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=None, separators=(",", ":"))
+        print(path, t1 - t0)
+        return
     x, iters, relres, st = oracle.pcg(coef, b, w.tol, 200_000)
     t2 = time.time()
     north, south = oracle.pole_values(pf, x)
@@ -74,4 +85,5 @@ def main(name):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "bipole_151x301x601")
+    # python tests/golden/make_oracle_samples.py NAME [--fixed-only]
+    main(sys.argv[1] if len(sys.argv) > 1 else "bipole_151x301x601", solve="--fixed-only" not in sys.argv)
