@@ -182,6 +182,94 @@ const char *pot3d_last_error(const pot3d_ctx *ctx);
 /* Library version string. */
 const char *pot3d_version(void);
 
+/* ------------------------------------------------------------------------
+ * Continuous-batching server.
+ *
+ * Many independent solves, each one the problem of Sec. 2.1-2.3 on its own
+ * grid with its own surface map Br, share the GPU.  Requests queue on the
+ * host.  Each pot3d_server_step:
+ *   1. retires the solves that ended in the previous step;
+ *   2. admits queued requests, in order, while a slot is free and their
+ *      device memory fits the budget;
+ *   3. advances every active solve by a fixed number of PCG iterations
+ *      (16), all in one replay of one captured HIP graph.
+ * As in Sec. 3.1, the vectors of a solve stay in device memory from
+ * admission to retirement.  Device memory per grid (tables and vectors) is
+ * cached and reused by later requests on the same grid.  A solve that has
+ * converged stops iterating at once, while the others go on.  Every result
+ * is bitwise the one pot3d_solve gives for the same request on a context of
+ * the same precision with the default launch shape.
+ * ------------------------------------------------------------------------ */
+typedef struct pot3d_server pot3d_server;
+
+typedef struct pot3d_request_info {
+    long long id;
+    int done;                /* 1 once the request has left the server          */
+    int status;              /* POT3D_* status of the solve (valid when done)   */
+    int iters;               /* PCG iterations (inner iterations summed in
+                                refined mode)                                   */
+    int outer;               /* defect-correction cycles (1 in FP64 mode)        */
+    int nr, nt, np;
+    double relres_true;      /* ||b - A Phi||/||b|| recomputed in FP64 at exit  */
+    double t_submit, t_admit, t_done;   /* seconds since server creation; -1 if
+                                           not reached                         */
+} pot3d_request_info;
+
+typedef struct pot3d_server_stats {
+    long long replays;       /* graph replays so far                            */
+    long long finished;      /* requests done (solved or failed)                */
+    int active, queued;      /* requests in slots and waiting                   */
+    int cached_contexts;     /* idle per-grid device contexts held for reuse    */
+    int max_slots;
+    int graph_iters;         /* PCG iterations per replay                       */
+    double used_bytes;       /* device bytes held by contexts (active + cached) */
+    double budget_bytes;
+} pot3d_server_stats;
+
+/*
+ * Create a server on `device`.
+ *   precision         POT3D_FP64 or POT3D_FP32_REFINED, for all requests
+ *   max_slots         1..64 concurrent solves
+ *   hbm_budget_bytes  device bytes the per-grid contexts may hold; 0 = 80% of
+ *                     the free device memory at creation
+ * Allocates the slot tables and captures the batched graph.
+ */
+int pot3d_server_create(int device, int precision, int max_slots, double hbm_budget_bytes,
+                        pot3d_server **out);
+
+/*
+ * Queue one solve.  Faces, nr, nt, np and br as in pot3d_create and
+ * pot3d_solve (host memory, copied); tol and maxit as in pot3d_solve.
+ * *id receives the request id.  Only validates and copies; no device work.
+ */
+int pot3d_server_submit(pot3d_server *sv, const double *r_faces, int nr, const double *t_faces, int nt,
+                        const double *p_faces, int np, const double *br, double tol, int maxit,
+                        long long *id);
+
+/*
+ * One scheduling step (retire, admit, one graph replay); returns after the
+ * replay has finished.  Out (each may be NULL): active slots, queued requests,
+ * and requests finished so far.  A request that cannot run on this server (a
+ * grid whose launch does not fit a slot, or whose context cannot be
+ * allocated) finishes with that error status and no Phi.
+ */
+int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long *n_finished);
+
+/*
+ * State of request `id` into *info (may be NULL).  Once it is done and phi is
+ * not NULL, Phi (host, nr*nt*np, phi-fastest) is copied out and the request
+ * is forgotten; later calls with its id return POT3D_EINVAL.
+ */
+int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_request_info *info);
+
+int pot3d_server_get_stats(const pot3d_server *sv, pot3d_server_stats *out);
+
+/* Waits for the device, then frees every context and the server.  NULL is a no-op. */
+void pot3d_server_destroy(pot3d_server *sv);
+
+/* Message of the last error on sv (sv = NULL: the thread's last create error). */
+const char *pot3d_server_last_error(const pot3d_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,14 +30,19 @@
 #include <string>
 #include <vector>
 
-#include "kernels.hpp"
-#include "pot3d.h"
+#include "context.hpp"
 
-using namespace pot3d;
-
-namespace {
+namespace pot3d {
+namespace host {
 
 thread_local std::string g_thread_error;
+
+int fail(pot3d_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_thread_error = msg;
+    return code;
+}
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
@@ -48,78 +53,6 @@ int env_int(const char *name, int dflt)
     return std::atoi(s);
 }
 
-}  // namespace
-
-struct pot3d_ctx {
-    int device = 0;
-    int nr = 0, nt = 0, np = 0, pitch = 0;
-    long long n = 0, npad = 0;
-    int precision = POT3D_FP64;
-    int tile_p = kTileMarch8, tile_r = kTileWave2, tile_o = kTileWave2;
-    int max_blocks = 0;
-    int num_cu = 256;
-    int graph_m = 16;
-    GridArgs grid_p{}, grid_r{}, grid_o{};   // update-p, update-r, other passes
-
-    std::vector<double> rf, tf, pf;
-    std::vector<RowCoef> rows_h;
-    std::vector<double> dphi_h, ih_h, bfac_h;
-
-    // device memory
-    RowCoef *rows = nullptr;
-    double *dphi = nullptr, *ih = nullptr, *bfac = nullptr;
-    double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr};
-    double *bplane = nullptr, *br = nullptr, *partial = nullptr, *poles = nullptr;
-    DevScalars *sc = nullptr;
-    DevScalars *h_sc = nullptr;     // pinned: two status slots for polling
-    hipStream_t stream = nullptr;
-    hipEvent_t ev_poll[2] = {nullptr, nullptr};
-    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_loop0 = nullptr, ev_loop1 = nullptr;
-    hipGraphExec_t graph = nullptr;
-
-    // FP32-refined mode
-    float *r32 = nullptr, *p32[2] = {nullptr, nullptr}, *e32 = nullptr;
-    DevScalars *sc32 = nullptr;
-    hipGraphExec_t graph32 = nullptr;
-    double inner_tol = 1e-5;
-    int max_outer = 50;
-
-    bool have_solution = false;
-    pot3d_stats stats{};
-    std::string err;
-};
-
-namespace {
-
-int fail(pot3d_ctx *ctx, int code, const std::string &msg)
-{
-    if (ctx) ctx->err = msg;
-    else g_thread_error = msg;
-    return code;
-}
-
-#define HIP_TRY(ctx, call)                                                                   \
-    do {                                                                                     \
-        hipError_t e_ = (call);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail((ctx), e_ == hipErrorOutOfMemory ? POT3D_ENOMEM : POT3D_EDEVICE,     \
-                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
-    } while (0)
-
-// Restores the caller's current device on scope exit.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 bool finite_increasing(const double *a, int n1)
 {
@@ -261,6 +194,7 @@ void choose_launch(pot3d_ctx *c)
     c->tile_p = valid_tile(env_int("POT3D_TILE_P", all ? all : kTileMarch8), kTileMarch8);
     c->tile_r = valid_tile(env_int("POT3D_TILE_R", all ? all : kTileMarch8), kTileMarch8);
     c->tile_o = all ? all : kTileWave2;
+    if (c->serving) c->tile_p = c->tile_r = kTileMarch8;   // the batched kernels' tile
     const int tb = env_int("POT3D_TARGET_BLOCKS", 0);
     const int tp = env_int("POT3D_TARGET_BLOCKS_P", tb), tr = env_int("POT3D_TARGET_BLOCKS_R", tb);
     c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : resident_blocks(c, kUpdateP, c->tile_p) / 2);
@@ -414,12 +348,20 @@ int check_solve_args(pot3d_ctx *c, const void *br, const void *phi, double tol, 
     return POT3D_OK;
 }
 
-int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, DevScalars fin, int launches,
-                 int total_iters, int outer, double bytes_per_unknown, int *iters, double *relres_true);
+// b from Br and the starting x (phi0, or zero).
+int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMemcpyKind kind_in, hipStream_t s)
+{
+    const size_t rowb = (size_t)c->np * sizeof(double), pitchb = (size_t)c->pitch * sizeof(double);
+    const size_t nrows = (size_t)c->nr * c->nt;
+    c->have_solution = false;
+    HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, c->bplane, s));
+    if (phi0) HIP_TRY(c, copy_rows(c->x, pitchb, phi0, rowb, rowb, nrows, kind_in, s));
+    else HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
+    return POT3D_OK;
+}
 
-// FP64 Jacobi-PCG: r = b - A x0, first test, then graph replays until done.
-int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters,
-             double *relres_true)
+// FP64 start: scalars, p_old = 0, r = b - A x0 and the first residual test.
+int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit)
 {
     DevScalars init{};
     init.tol = tol;
@@ -427,7 +369,6 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     c->h_sc[0] = init;
     HIP_TRY(c, hipMemcpyAsync(c->sc, &c->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
     HIP_TRY(c, launch_fill<double>(c->p[0], c->npad, 0.0, s));
-
     StencilVecs<double> rv = base_vecs(c);
     rv.in = c->x;
     rv.r = c->r;
@@ -436,14 +377,64 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     rv.ignore_done = 1;
     HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
     HIP_TRY(c, launch_finish(kFinInit, c->sc, c->partial, c->grid_o.nblocks, s));
+    return POT3D_OK;
+}
 
+// FP64 Jacobi-PCG: start, then graph replays until done.
+int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters,
+             double *relres_true)
+{
+    int rc = start_fp64(c, s, tol, maxit);
+    if (rc != POT3D_OK) return rc;
     HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
     int launches = 0;
     DevScalars fin{};
-    int rc = replay_until_done(c, c->graph, c->sc, s, maxit, &launches, &fin);
+    rc = replay_until_done(c, c->graph, c->sc, s, maxit, &launches, &fin);
     if (rc != POT3D_OK) return rc;
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
     return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, 64.0, iters, relres_true);
+}
+
+// Refinement, outer step: r = b - A x in FP64, then the outer test.  The
+// scalar block must already hold tol (set once per solve).  Waits for the
+// result and returns it in *out.
+int refined_outer_check(pot3d_ctx *c, hipStream_t s, DevScalars *out)
+{
+    StencilVecs<double> rv = base_vecs(c);
+    rv.in = c->x;
+    rv.r = c->r;
+    rv.bplane = c->bplane;
+    rv.store_r = 1;
+    rv.ignore_done = 1;
+    HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
+    HIP_TRY(c, launch_finish(kFinOuter, c->sc, c->partial, c->grid_o.nblocks, s));
+    HIP_TRY(c, hipMemcpyAsync(&c->h_sc[0], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIP_TRY(c, hipStreamSynchronize(s));
+    *out = c->h_sc[0];
+    return POT3D_OK;
+}
+
+// Refinement, inner start: r32 = r / ||r||, e = 0, p = 0, and the FP32 PCG
+// start.  The inner solve goes no further than the outer target needs: an
+// inner reduction of tol / relres (with a factor 2 margin) already meets it.
+int refined_start_inner(pot3d_ctx *c, hipStream_t s, double tol, int maxit_left, double outer_relres)
+{
+    const int nb_dots = std::max(1, std::min(c->max_blocks, c->nr * c->nt));
+    HIP_TRY(c, launch_cast_residual(c->r, c->r32, c->e32, c->p32[0], c->npad, c->sc, s));
+    DevScalars in{};
+    in.tol = std::max(c->inner_tol, 0.5 * tol / outer_relres);
+    in.maxit = maxit_left;
+    c->h_sc[1] = in;
+    HIP_TRY(c, hipMemcpyAsync(c->sc32, &c->h_sc[1], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIP_TRY(c, launch_dots_rz(c->grid_o, c->r32, c->partial, nb_dots, s));
+    HIP_TRY(c, launch_finish(kFinInner, c->sc32, c->partial, nb_dots, s));
+    return POT3D_OK;
+}
+
+int refined_correct(pot3d_ctx *c, hipStream_t s)
+{
+    HIP_TRY(c, launch_add_correction(c->x, c->e32, c->npad, c->sc, s));
+    return POT3D_OK;
 }
 
 // FP32-refined: outer FP64 defect correction around FP32 Jacobi-PCG solves.
@@ -462,36 +453,18 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
     HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
     int launches = 0, total = 0, outer = 0;
     DevScalars out{};
-    const int nb_dots = std::max(1, std::min(c->max_blocks, c->nr * c->nt));
     for (;;) {
-        StencilVecs<double> rv = base_vecs(c);
-        rv.in = c->x;
-        rv.r = c->r;
-        rv.bplane = c->bplane;
-        rv.store_r = 1;
-        rv.ignore_done = 1;
-        HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
-        HIP_TRY(c, launch_finish(kFinOuter, c->sc, c->partial, c->grid_o.nblocks, s));
-        HIP_TRY(c, hipMemcpyAsync(&c->h_sc[0], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        HIP_TRY(c, hipStreamSynchronize(s));
-        out = c->h_sc[0];
+        int rc = refined_outer_check(c, s, &out);
+        if (rc != POT3D_OK) return rc;
         if (out.done) break;
         if (outer >= c->max_outer || total >= maxit) {
             out.status = POT3D_ENOCONV;
             break;
         }
-        HIP_TRY(c, launch_cast_residual(c->r, c->r32, c->e32, c->p32[0], c->npad, c->sc, s));
-        // Solve no further than the outer target needs: an inner reduction of
-        // tol / relres (with a factor 2 margin) already meets it.
-        DevScalars in{};
-        in.tol = std::max(c->inner_tol, 0.5 * tol / out.relres);
-        in.maxit = maxit - total;
-        c->h_sc[1] = in;
-        HIP_TRY(c, hipMemcpyAsync(c->sc32, &c->h_sc[1], sizeof(DevScalars), hipMemcpyHostToDevice, s));
-        HIP_TRY(c, launch_dots_rz(c->grid_o, c->r32, c->partial, nb_dots, s));
-        HIP_TRY(c, launch_finish(kFinInner, c->sc32, c->partial, nb_dots, s));
+        rc = refined_start_inner(c, s, tol, maxit - total, out.relres);
+        if (rc != POT3D_OK) return rc;
         DevScalars inner{};
-        int rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, &launches, &inner);
+        rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, &launches, &inner);
         if (rc != POT3D_OK) return rc;
         total += inner.k;
         ++outer;
@@ -499,7 +472,8 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
             out.status = POT3D_EBREAKDOWN;
             break;
         }
-        HIP_TRY(c, launch_add_correction(c->x, c->e32, c->npad, c->sc, s));
+        rc = refined_correct(c, s);
+        if (rc != POT3D_OK) return rc;
     }
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
     return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, 32.0, iters, relres_true);
@@ -510,13 +484,9 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
 int run_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMemcpyKind kind_in, double *phi_out,
               hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters, double *relres_true)
 {
-    const size_t rowb = (size_t)c->np * sizeof(double), pitchb = (size_t)c->pitch * sizeof(double);
-    const size_t nrows = (size_t)c->nr * c->nt;
-    c->have_solution = false;
     HIP_TRY(c, hipEventRecord(c->ev_t0, s));
-    HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, c->bplane, s));
-    if (phi0) HIP_TRY(c, copy_rows(c->x, pitchb, phi0, rowb, rowb, nrows, kind_in, s));
-    else HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
+    int rc = prepare_solve(c, br_dev, phi0, kind_in, s);
+    if (rc != POT3D_OK) return rc;
     if (c->precision == POT3D_FP32_REFINED) return run_refined(c, phi_out, kind_out, s, tol, maxit, iters, relres_true);
     return run_fp64(c, phi_out, kind_out, s, tol, maxit, iters, relres_true);
 }
@@ -630,35 +600,8 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
     return rc;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *pot3d_version(void)
-{
-    return checked_build() ? "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG, checked indices)"
-                           : "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG)";
-}
-
-int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer)
-{
-    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
-    if (ctx->precision != POT3D_FP32_REFINED) return fail(ctx, POT3D_EINVAL, "context is not FP32-refined");
-    if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(ctx, POT3D_EINVAL, "inner_tol must be in (0, 1)");
-    if (max_outer < 1) return fail(ctx, POT3D_EINVAL, "max_outer must be >= 1");
-    ctx->inner_tol = inner_tol;
-    ctx->max_outer = max_outer;
-    return POT3D_OK;
-}
-
-const char *pot3d_last_error(const pot3d_ctx *ctx)
-{
-    if (ctx) return ctx->err.c_str();
-    return g_thread_error.c_str();
-}
-
-int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,
-                 int upper_bc, int precision, int device, pot3d_ctx **out)
+int create_context(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,
+                   int upper_bc, int precision, int device, bool serving, pot3d_ctx **out)
 {
     int v = validate_grid(r_faces, nr, t_faces, nt, p_faces, np, upper_bc, precision, out);
     if (v != POT3D_OK) return v;
@@ -671,6 +614,7 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
 
     pot3d_ctx *c = new pot3d_ctx();
     c->device = device;
+    c->serving = serving;
     c->nr = nr;
     c->nt = nt;
     c->np = np;
@@ -745,9 +689,10 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
         CREATE_TRY(hipStreamSynchronize(c->stream));
     }
 #undef CREATE_TRY
-    // The iteration graphs are captured once, on the idle context stream.
-    int gc = capture_iterations<double>(c, c->r, c->p[0], c->p[1], c->x, c->sc, &c->graph);
-    if (gc == POT3D_OK && precision == POT3D_FP32_REFINED)
+    // The iteration graphs are captured once, on the idle context stream
+    // (serving slots iterate inside the server's batched graph instead).
+    int gc = serving ? POT3D_OK : capture_iterations<double>(c, c->r, c->p[0], c->p[1], c->x, c->sc, &c->graph);
+    if (gc == POT3D_OK && precision == POT3D_FP32_REFINED && !serving)
         gc = capture_iterations<float>(c, c->r32, c->p32[0], c->p32[1], c->e32, c->sc32, &c->graph32);
     if (gc != POT3D_OK) {
         std::string m = c->err;
@@ -756,6 +701,52 @@ int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, c
     }
     *out = c;
     return POT3D_OK;
+}
+
+size_t context_bytes(const pot3d_ctx *c)
+{
+    size_t b = (size_t)c->npad * sizeof(double) * 4 + (size_t)c->nt * c->pitch * sizeof(double) +
+               (size_t)c->nt * c->np * sizeof(double) + c->rows_h.size() * sizeof(RowCoef) +
+               (size_t)3 * c->max_blocks * sizeof(double) + (size_t)2 * c->nr * sizeof(double);
+    if (c->precision == POT3D_FP32_REFINED) b += (size_t)c->npad * sizeof(float) * 4;
+    return b;
+}
+
+}  // namespace host
+}  // namespace pot3d
+
+using namespace pot3d;
+using namespace pot3d::host;
+
+extern "C" {
+
+const char *pot3d_version(void)
+{
+    return checked_build() ? "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG, checked indices)"
+                           : "pot3d-mi355x 0.2 (gfx950, FP64 and FP32-refined Jacobi-PCG)";
+}
+
+int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (ctx->precision != POT3D_FP32_REFINED) return fail(ctx, POT3D_EINVAL, "context is not FP32-refined");
+    if (!(inner_tol > 0.0 && inner_tol < 1.0)) return fail(ctx, POT3D_EINVAL, "inner_tol must be in (0, 1)");
+    if (max_outer < 1) return fail(ctx, POT3D_EINVAL, "max_outer must be >= 1");
+    ctx->inner_tol = inner_tol;
+    ctx->max_outer = max_outer;
+    return POT3D_OK;
+}
+
+const char *pot3d_last_error(const pot3d_ctx *ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_thread_error.c_str();
+}
+
+int pot3d_create(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,
+                 int upper_bc, int precision, int device, pot3d_ctx **out)
+{
+    return create_context(r_faces, nr, t_faces, nt, p_faces, np, upper_bc, precision, device, false, out);
 }
 
 int pot3d_solve(pot3d_ctx *ctx, const double *br, double tol, int maxit, const double *phi0, double *phi, int *iters,

@@ -1,0 +1,116 @@
+// context.hpp -- the solver context and the host-side steps shared by the
+// single-solve C ABI (api.hip) and the batching server (server.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "pot3d.h"
+
+using pot3d::BatchFin;
+using pot3d::BatchSlot;
+using pot3d::DevScalars;
+using pot3d::GridArgs;
+using pot3d::RowCoef;
+using pot3d::StencilVecs;
+using pot3d::kTileMarch8;
+using pot3d::kTileWave2;
+
+struct pot3d_ctx {
+    int device = 0;
+    int nr = 0, nt = 0, np = 0, pitch = 0;
+    long long n = 0, npad = 0;
+    int precision = POT3D_FP64;
+    int tile_p = kTileMarch8, tile_r = kTileWave2, tile_o = kTileWave2;
+    int max_blocks = 0;
+    int num_cu = 256;
+    int graph_m = 16;
+    GridArgs grid_p{}, grid_r{}, grid_o{};   // update-p, update-r, other passes
+
+    std::vector<double> rf, tf, pf;
+    std::vector<RowCoef> rows_h;
+    std::vector<double> dphi_h, ih_h, bfac_h;
+
+    // device memory
+    RowCoef *rows = nullptr;
+    double *dphi = nullptr, *ih = nullptr, *bfac = nullptr;
+    double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr};
+    double *bplane = nullptr, *br = nullptr, *partial = nullptr, *poles = nullptr;
+    DevScalars *sc = nullptr;
+    DevScalars *h_sc = nullptr;     // pinned: two status slots for polling
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_poll[2] = {nullptr, nullptr};
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr, ev_loop0 = nullptr, ev_loop1 = nullptr;
+    hipGraphExec_t graph = nullptr;
+
+    // FP32-refined mode
+    float *r32 = nullptr, *p32[2] = {nullptr, nullptr}, *e32 = nullptr;
+    DevScalars *sc32 = nullptr;
+    hipGraphExec_t graph32 = nullptr;
+    double inner_tol = 1e-5;
+    int max_outer = 50;
+
+    bool serving = false;         // a batching-server slot (launch shapes fixed to the batched kernels)
+    bool have_solution = false;
+    pot3d_stats stats{};
+    std::string err;
+};
+
+namespace pot3d {
+namespace host {
+
+// Record msg as the context's (or, for ctx = NULL, the thread's) last error.
+int fail(pot3d_ctx *ctx, int code, const std::string &msg);
+
+#define HIP_TRY(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? POT3D_ENOMEM : POT3D_EDEVICE,     \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+int validate_grid(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,
+                  int precision, pot3d_ctx **out);
+// Allocate a context on `device` (tables, vectors, graphs).  serving = true:
+// launch shapes fixed to the batched kernels' tile and no graph capture.
+int create_context(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,
+                   int precision, int device, bool serving, pot3d_ctx **out);
+void free_ctx(pot3d_ctx *c);
+// Device bytes held by a context.
+size_t context_bytes(const pot3d_ctx *c);
+StencilVecs<double> base_vecs(pot3d_ctx *c);
+// b from Br (device) and the starting x (phi0 or zero).
+int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMemcpyKind kind_in, hipStream_t s);
+// FP64: r = b - A x, p_old = 0, scalars initialised, first residual test.
+int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit);
+// Refined: r = b - A x in FP64 and the outer test; waits, then *out holds the scalars.
+int refined_outer_check(pot3d_ctx *c, hipStream_t s, DevScalars *out);
+// Refined: normalised FP32 residual, e = 0, and the inner PCG start.
+int refined_start_inner(pot3d_ctx *c, hipStream_t s, double tol, int maxit_left, double outer_relres);
+// Refined: x += ||r|| e.
+int refined_correct(pot3d_ctx *c, hipStream_t s);
+// True residual, pole values, Phi out, statistics; returns the solve status.
+int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, DevScalars fin, int launches,
+                 int total_iters, int outer, double bytes_per_unknown, int *iters, double *relres_true);
+
+}  // namespace host
+}  // namespace pot3d

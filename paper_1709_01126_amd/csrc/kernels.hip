@@ -62,10 +62,13 @@ __device__ __forceinline__ V diag_at(const RowCoef &rc, V dph, V ihm, V ihk)
     return vfma<V>(dph, (V)rc.s, (V)rc.pq * (ihm + ihk));
 }
 
+// The LDS-plane marching pass for one workgroup; b is the workgroup's index
+// within its own launch shape (blockIdx.x for a single solve, the index inside
+// the slot for a batched launch).
 template <int TJ, int MODE, typename V>
-__global__ void __launch_bounds__(kThreads)
-stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
-              const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
+__device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<V> &v, const RowCoef *__restrict__ rows,
+                                           const V *__restrict__ vin, const V *__restrict__ vpold, V *__restrict__ vout,
+                                           V *__restrict__ vout2, const int b)
 {
     static_assert(TJ % kWaves == 0 && 2 * TJ <= kWave, "tile rows");
     constexpr int M = TJ / kWaves;   // rows per wavefront
@@ -80,7 +83,6 @@ stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, co
     // logical tiles and shares their halos in its L2.  The phi tile varies
     // fastest: the phi-halo cells of a tile sit in 128-byte lines owned by its
     // phi neighbours, which then run beside it on the same XCD.
-    const int b = blockIdx.x;
     const int per = g.nblocks / kXcds;
     int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
     if (g.reverse) L = g.nblocks - 1 - L;
@@ -299,6 +301,33 @@ stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, co
             v.partial[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
     }
+}
+
+template <int TJ, int MODE, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
+              const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
+{
+    march_body<TJ, MODE, V>(g, v, rows, vin, vpold, vout, vout2, blockIdx.x);
+}
+
+// Batched pass: one launch covers every active slot of a slot table.  Slot q
+// owns workgroups [offset, offset + nblocks) of the grid (offsets are
+// multiples of 8, so the XCD-aware tile order inside a slot is unchanged), and
+// each slot runs exactly the arithmetic of its single-solve launch.
+template <int TJ, int MODE, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_march_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
+{
+    const int bid = blockIdx.x;
+    int s = -1;
+    for (int q = 0; q < nslots; ++q) {
+        const BatchSlot<V> &sl = slots[q];
+        if (sl.active && bid >= sl.offset && bid < sl.offset + sl.g.nblocks) s = q;
+    }
+    if (s < 0) return;
+    const BatchSlot<V> &sl = slots[s];
+    march_body<TJ, MODE, V>(sl.g, sl.v, sl.g.rows, sl.v.in, sl.v.pold, sl.out, sl.v.x, bid - sl.offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -651,8 +680,7 @@ __device__ __forceinline__ void block_sums(const double *partial, int nb, int nc
     for (int c = 0; c < ncomp; ++c) out[c] = sh[c][0];
 }
 
-__global__ void __launch_bounds__(kFinThreads)
-finish_kernel(int which, DevScalars *sc, const double *partial, int nb)
+__device__ __forceinline__ void finish_body(int which, DevScalars *sc, const double *partial, int nb)
 {
     // the start-of-solve and end-of-solve finishers run whatever the done flag says
     const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner;
@@ -775,6 +803,21 @@ finish_kernel(int which, DevScalars *sc, const double *partial, int nb)
         sc->done = (!(rnorm > 0.0) || !isfinite(rnorm) || sc->maxit <= 0) ? 1 : 0;
         if (!isfinite(rnorm)) sc->status = POT3D_EBREAKDOWN;
     }
+}
+
+__global__ void __launch_bounds__(kFinThreads)
+finish_kernel(int which, DevScalars *sc, const double *partial, int nb)
+{
+    finish_body(which, sc, partial, nb);
+}
+
+// Batched finisher: workgroup q advances the scalars of slot q.
+__global__ void __launch_bounds__(kFinThreads)
+finish_batch(int which, const BatchFin *__restrict__ fins, int nslots)
+{
+    const int q = blockIdx.x;
+    if (q >= nslots || !fins[q].active) return;
+    finish_body(which, fins[q].sc, fins[q].partial, fins[q].nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -990,6 +1033,27 @@ template hipError_t launch_stencil<double>(int, int, const GridArgs &, const Ste
                                           hipEvent_t, hipEvent_t);
 template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t,
                                          hipEvent_t, hipEvent_t);
+
+template <typename V>
+hipError_t launch_stencil_batch(int mode, const BatchSlot<V> *slots, int nslots, int total_blocks, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 grid(total_blocks), block(kThreads);
+    switch (mode) {
+    case kUpdateP: stencil_march_batch<8, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateR: stencil_march_batch<8, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_stencil_batch<double>(int, const BatchSlot<double> *, int, int, hipStream_t);
+template hipError_t launch_stencil_batch<float>(int, const BatchSlot<float> *, int, int, hipStream_t);
+
+hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipStream_t s)
+{
+    finish_batch<<<nslots, kFinThreads, 0, s>>>(which, fins, nslots);
+    return hipGetLastError();
+}
 
 hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s)
 {

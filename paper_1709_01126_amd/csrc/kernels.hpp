@@ -41,6 +41,11 @@ bool checked_build();
 
 hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s);
 
+// Batched passes over a device slot table (tile kTileMarch8 in every slot).
+template <typename V>
+hipError_t launch_stencil_batch(int mode, const BatchSlot<V> *slots, int nslots, int total_blocks, hipStream_t s);
+hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipStream_t s);
+
 hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, int nt, int np, int pitch,
                       double *bplane, hipStream_t s);
 

@@ -1,0 +1,604 @@
+// server.hip -- continuous batching of potential-field solves on one GPU.
+//
+// Requests (a grid, a surface map Br, tol, maxit) queue on the host.  Each
+// step of the server:
+//   1. retires finished slots: true residual, pole values, Phi copied out.
+//      In FP32-refined mode a finished inner solve instead gets its
+//      correction, an FP64 outer test, and either a new inner solve or
+//      retirement;
+//   2. admits queued requests while a slot is free and their device
+//      footprint fits the HBM budget.  Per-grid contexts (tables and vectors)
+//      are cached and reused; idle ones are evicted oldest first when the
+//      budget needs it;
+//   3. replays one captured graph of m batched PCG iterations.  Each kernel of
+//      it covers every active slot (a slot table in device memory maps
+//      workgroups to slots), and slots that have converged are masked by their
+//      own done flags.
+// The graph is captured once for a fixed slot capacity and reads the slot
+// tables at run time, so requests join and leave between replays without
+// recapture.  Every slot runs exactly the launch shape, tile order and
+// reduction order of a single solve on the same grid, so each result is
+// bitwise the one the request would get alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "context.hpp"
+
+using namespace pot3d;
+using namespace pot3d::host;
+
+namespace {
+
+struct Request {
+    long long id = 0;
+    int nr = 0, nt = 0, np = 0;
+    std::vector<double> rf, tf, pf, br;
+    double tol = 0.0;
+    int maxit = 0;
+    std::vector<double> phi;
+    int status = POT3D_OK, iters = 0, outer = 0;
+    double relres_true = 0.0;
+    double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
+    bool done = false;
+};
+
+struct Slot {
+    pot3d_ctx *ctx = nullptr;
+    Request *req = nullptr;
+    bool active = false;
+    int total_inner = 0, outer = 0, launches = 0;
+};
+
+constexpr int kBlockAlign = 8;   // slot offsets keep the XCD of a workgroup unchanged
+
+int round_up(int v, int a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct pot3d_server {
+    int device = 0, precision = POT3D_FP64, max_slots = 0, graph_m = 16;
+    int per_slot_blocks = 0, capacity = 0;
+    size_t budget = 0, used = 0;
+    hipStream_t stream = nullptr;
+    std::deque<Request *> queue;
+    std::map<long long, std::unique_ptr<Request>> requests;
+    long long next_id = 1, finished = 0, replays = 0;
+    std::vector<Slot> slots;
+    std::vector<pot3d_ctx *> idle;   // cached contexts, oldest first
+    // slot tables [parity][slot]: update-p and update-r, FP64 or FP32
+    BatchSlot<double> *d_p64[2] = {nullptr, nullptr}, *d_r64[2] = {nullptr, nullptr};
+    BatchSlot<float> *d_p32[2] = {nullptr, nullptr}, *d_r32[2] = {nullptr, nullptr};
+    BatchFin *d_finp = nullptr, *d_finr = nullptr;
+    std::vector<BatchSlot<double>> h_p64[2], h_r64[2];
+    std::vector<BatchSlot<float>> h_p32[2], h_r32[2];
+    std::vector<BatchFin> h_finp, h_finr;
+    DevScalars *h_status = nullptr;   // pinned, one per slot
+    hipGraphExec_t graph = nullptr;
+    std::chrono::steady_clock::time_point t0;
+    std::string err;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace {
+
+thread_local std::string g_server_error;
+
+int sfail(pot3d_server *sv, int code, const std::string &msg)
+{
+    if (sv) sv->err = msg;
+    else g_server_error = msg;
+    return code;
+}
+
+#define SV_TRY(sv, call)                                                                             \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return sfail((sv), e_ == hipErrorOutOfMemory ? POT3D_ENOMEM : POT3D_EDEVICE,             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                        \
+    } while (0)
+
+#define SV_CALL(sv, ctx, call)                                                                       \
+    do {                                                                                             \
+        int rc_ = (call);                                                                            \
+        if (rc_ != POT3D_OK) return sfail((sv), rc_, pot3d_last_error(ctx));                          \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count)
+{
+    return hipMalloc(reinterpret_cast<void **>(p), std::max<size_t>(1, count) * sizeof(T));
+}
+
+template <typename V>
+int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr)
+{
+    hipStream_t s = sv->stream;
+    SV_TRY(sv, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < sv->graph_m && e == hipSuccess; ++it) {
+        e = launch_stencil_batch<V>(kUpdateP, dp[it & 1], sv->max_slots, sv->capacity, s);
+        if (e == hipSuccess) e = launch_finish_batch(kFinSigma, sv->d_finp, sv->max_slots, s);
+        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, dr[it & 1], sv->max_slots, sv->capacity, s);
+        if (e == hipSuccess) e = launch_finish_batch(kFinRho, sv->d_finr, sv->max_slots, s);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return sfail(sv, POT3D_EDEVICE, std::string("batched graph capture: ") +
+                                            hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipError_t e3 = hipGraphInstantiate(&sv->graph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return sfail(sv, POT3D_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return POT3D_OK;
+}
+
+// Slot tables from the current slots (inactive slots own no workgroups).
+template <typename V>
+void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<BatchSlot<V>> *hr)
+{
+    int offp = 0, offr = 0;
+    for (int q = 0; q < sv->max_slots; ++q) {
+        const Slot &sl = sv->slots[q];
+        for (int par = 0; par < 2; ++par) {
+            hp[par][q] = BatchSlot<V>{};
+            hr[par][q] = BatchSlot<V>{};
+        }
+        sv->h_finp[q] = BatchFin{};
+        sv->h_finr[q] = BatchFin{};
+        if (!sl.active) continue;
+        pot3d_ctx *c = sl.ctx;
+        V *r, *x, *p[2];
+        DevScalars *sc;
+        if constexpr (std::is_same<V, double>::value) {
+            r = c->r;
+            x = c->x;
+            p[0] = c->p[0];
+            p[1] = c->p[1];
+            sc = c->sc;
+        } else {
+            r = c->r32;
+            x = c->e32;
+            p[0] = c->p32[0];
+            p[1] = c->p32[1];
+            sc = c->sc32;
+        }
+        for (int par = 0; par < 2; ++par) {
+            BatchSlot<V> &a = hp[par][q];
+            a.g = c->grid_p;
+            a.v.in = r;
+            a.v.pold = p[par];
+            a.v.pnew = p[par ^ 1];
+            a.v.sc = sc;
+            a.v.partial = c->partial;
+            a.out = p[par ^ 1];
+            a.offset = offp;
+            a.active = 1;
+            BatchSlot<V> &b = hr[par][q];
+            b.g = c->grid_r;
+            b.v.in = p[par ^ 1];
+            b.v.r = r;
+            b.v.x = x;
+            b.v.sc = sc;
+            b.v.partial = c->partial;
+            b.out = r;
+            b.offset = offr;
+            b.active = 1;
+        }
+        sv->h_finp[q] = BatchFin{sc, c->partial, c->grid_p.nblocks, 1};
+        sv->h_finr[q] = BatchFin{sc, c->partial, c->grid_r.nblocks, 1};
+        offp += round_up(c->grid_p.nblocks, kBlockAlign);
+        offr += round_up(c->grid_r.nblocks, kBlockAlign);
+    }
+}
+
+int upload_tables(pot3d_server *sv)
+{
+    hipStream_t s = sv->stream;
+    const size_t n = sv->max_slots;
+    if (sv->precision == POT3D_FP64) {
+        fill_tables<double>(sv, sv->h_p64, sv->h_r64);
+        for (int par = 0; par < 2; ++par) {
+            SV_TRY(sv, hipMemcpyAsync(sv->d_p64[par], sv->h_p64[par].data(), n * sizeof(BatchSlot<double>),
+                                      hipMemcpyHostToDevice, s));
+            SV_TRY(sv, hipMemcpyAsync(sv->d_r64[par], sv->h_r64[par].data(), n * sizeof(BatchSlot<double>),
+                                      hipMemcpyHostToDevice, s));
+        }
+    } else {
+        fill_tables<float>(sv, sv->h_p32, sv->h_r32);
+        for (int par = 0; par < 2; ++par) {
+            SV_TRY(sv, hipMemcpyAsync(sv->d_p32[par], sv->h_p32[par].data(), n * sizeof(BatchSlot<float>),
+                                      hipMemcpyHostToDevice, s));
+            SV_TRY(sv, hipMemcpyAsync(sv->d_r32[par], sv->h_r32[par].data(), n * sizeof(BatchSlot<float>),
+                                      hipMemcpyHostToDevice, s));
+        }
+    }
+    SV_TRY(sv, hipMemcpyAsync(sv->d_finp, sv->h_finp.data(), n * sizeof(BatchFin), hipMemcpyHostToDevice, s));
+    SV_TRY(sv, hipMemcpyAsync(sv->d_finr, sv->h_finr.data(), n * sizeof(BatchFin), hipMemcpyHostToDevice, s));
+    // the tables are pageable host vectors: finish the copies before they change
+    SV_TRY(sv, hipStreamSynchronize(s));
+    return POT3D_OK;
+}
+
+bool same_grid(const pot3d_ctx *c, const Request *r)
+{
+    return c->nr == r->nr && c->nt == r->nt && c->np == r->np && c->rf == r->rf && c->tf == r->tf && c->pf == r->pf;
+}
+
+void release_context(pot3d_server *sv, pot3d_ctx *c)
+{
+    sv->idle.push_back(c);
+}
+
+void evict_one(pot3d_server *sv)
+{
+    pot3d_ctx *c = sv->idle.front();
+    sv->idle.erase(sv->idle.begin());
+    sv->used -= context_bytes(c);
+    free_ctx(c);
+}
+
+// A context for r: a cached one with the same grid, or a new one if the budget
+// allows (evicting idle contexts oldest first).  *ctx = NULL: not now.
+int acquire_context(pot3d_server *sv, Request *r, pot3d_ctx **ctx)
+{
+    *ctx = nullptr;
+    for (size_t q = 0; q < sv->idle.size(); ++q) {
+        if (same_grid(sv->idle[q], r)) {
+            *ctx = sv->idle[q];
+            sv->idle.erase(sv->idle.begin() + q);
+            return POT3D_OK;
+        }
+    }
+    // estimate before allocating: 4 FP64 vectors (+4 FP32) of the padded size, plus tables
+    const long long pitch = (r->np + 7) / 8 * 8;
+    const size_t need = (size_t)r->nr * r->nt * pitch * (sv->precision == POT3D_FP32_REFINED ? 48 : 32) +
+                        (size_t)r->nr * r->nt * 64 + (size_t)r->nt * pitch * 16 + (1u << 20);
+    while (sv->used + need > sv->budget && !sv->idle.empty()) evict_one(sv);
+    if (sv->used + need > sv->budget) return POT3D_OK;   // wait for a slot to retire
+    pot3d_ctx *c = nullptr;
+    int rc = create_context(r->rf.data(), r->nr, r->tf.data(), r->nt, r->pf.data(), r->np, POT3D_UPPER_SOURCE_SURFACE,
+                            sv->precision, sv->device, true, &c);
+    if (rc != POT3D_OK) return sfail(sv, rc, pot3d_last_error(nullptr));
+    if (c->grid_p.nblocks > sv->per_slot_blocks || c->grid_r.nblocks > sv->per_slot_blocks) {
+        free_ctx(c);
+        return sfail(sv, POT3D_EINVAL, "grid needs more workgroups per launch than a server slot holds");
+    }
+    sv->used += context_bytes(c);
+    *ctx = c;
+    return POT3D_OK;
+}
+
+void complete(pot3d_server *sv, Slot &sl, int status, int iters, int outer, double relres_true)
+{
+    Request *r = sl.req;
+    r->status = status;
+    r->iters = iters;
+    r->outer = outer;
+    r->relres_true = relres_true;
+    r->t_done = sv->now();
+    r->done = true;
+    ++sv->finished;
+    release_context(sv, sl.ctx);
+    sl = Slot{};
+}
+
+// Retire a slot whose solve has ended: true residual, pole values, Phi out.
+int retire(pot3d_server *sv, Slot &sl, DevScalars fin, int total_iters, int outer)
+{
+    pot3d_ctx *c = sl.ctx;
+    Request *r = sl.req;
+    r->phi.resize((size_t)r->nr * r->nt * r->np);
+    int iters = 0;
+    double rel = 0.0;
+    SV_TRY(sv, hipEventRecord(c->ev_loop1, sv->stream));
+    const int rc = finish_solve(c, r->phi.data(), hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
+                                sv->precision == POT3D_FP32_REFINED ? 32.0 : 64.0, &iters, &rel);
+    if (rc != POT3D_OK && rc != POT3D_ENOCONV && rc != POT3D_EBREAKDOWN) return sfail(sv, rc, pot3d_last_error(c));
+    complete(sv, sl, rc, iters, outer, rel);
+    return POT3D_OK;
+}
+
+// Refined slot: the outer test, then retire or start the next inner solve.
+int refined_advance(pot3d_server *sv, Slot &sl)
+{
+    pot3d_ctx *c = sl.ctx;
+    Request *r = sl.req;
+    DevScalars out{};
+    SV_CALL(sv, c, refined_outer_check(c, sv->stream, &out));
+    if (out.done) return retire(sv, sl, out, sl.total_inner, sl.outer);
+    if (sl.outer >= c->max_outer || sl.total_inner >= r->maxit) {
+        out.status = POT3D_ENOCONV;
+        return retire(sv, sl, out, sl.total_inner, sl.outer);
+    }
+    SV_CALL(sv, c, refined_start_inner(c, sv->stream, r->tol, r->maxit - sl.total_inner, out.relres));
+    return POT3D_OK;
+}
+
+int admit(pot3d_server *sv, Slot &sl, Request *r, pot3d_ctx *c)
+{
+    hipStream_t s = sv->stream;
+    sl = Slot{};
+    sl.ctx = c;
+    sl.req = r;
+    sl.active = true;
+    r->t_admit = sv->now();
+    SV_TRY(sv, hipEventRecord(c->ev_t0, s));
+    SV_TRY(sv, hipMemcpyAsync(c->br, r->br.data(), r->br.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    SV_CALL(sv, c, prepare_solve(c, c->br, nullptr, hipMemcpyHostToDevice, s));
+    SV_TRY(sv, hipEventRecord(c->ev_loop0, s));
+    if (sv->precision == POT3D_FP64) {
+        SV_CALL(sv, c, start_fp64(c, s, r->tol, r->maxit));
+        return POT3D_OK;
+    }
+    DevScalars init{};
+    init.tol = r->tol;
+    init.maxit = r->maxit;
+    c->h_sc[0] = init;
+    SV_TRY(sv, hipMemcpyAsync(c->sc, &c->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    return refined_advance(sv, sl);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pot3d_server_last_error(const pot3d_server *sv) { return sv ? sv->err.c_str() : g_server_error.c_str(); }
+
+int pot3d_server_create(int device, int precision, int max_slots, double hbm_budget_bytes, pot3d_server **out)
+{
+    if (!out) return sfail(nullptr, POT3D_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (precision != POT3D_FP64 && precision != POT3D_FP32_REFINED) return sfail(nullptr, POT3D_EINVAL, "bad precision");
+    if (max_slots < 1 || max_slots > 64) return sfail(nullptr, POT3D_EINVAL, "max_slots must be in [1, 64]");
+    if (!(hbm_budget_bytes >= 0.0) || !std::isfinite(hbm_budget_bytes))
+        return sfail(nullptr, POT3D_EINVAL, "hbm_budget_bytes must be finite and >= 0 (0: 80% of free memory)");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return sfail(nullptr, POT3D_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return sfail(nullptr, POT3D_EINVAL, "device index out of range");
+    DeviceGuard guard(device);
+    if (!guard.ok) return sfail(nullptr, POT3D_EDEVICE, "hipSetDevice failed");
+
+    auto sv = std::make_unique<pot3d_server>();
+    sv->device = device;
+    sv->precision = precision;
+    sv->max_slots = max_slots;
+    sv->t0 = std::chrono::steady_clock::now();
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return sfail(nullptr, POT3D_EDEVICE, "hipMemGetInfo failed");
+    sv->budget = hbm_budget_bytes > 0.0 ? (size_t)hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
+    // a slot holds up to half of the resident workgroups of the batched kernels
+    hipDeviceProp_t prop{};
+    const int ncu = (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+                        ? prop.multiProcessorCount
+                        : 256;
+    const int per_cu = precision == POT3D_FP64 ? stencil_blocks_per_cu<double>(kUpdateP, kTileMarch8)
+                                               : stencil_blocks_per_cu<float>(kUpdateP, kTileMarch8);
+    sv->per_slot_blocks = round_up(std::max(1024, std::max(1, per_cu) * ncu), kBlockAlign);
+    sv->capacity = sv->per_slot_blocks * max_slots;
+    sv->slots.assign(max_slots, Slot{});
+    for (int par = 0; par < 2; ++par) {
+        sv->h_p64[par].assign(max_slots, BatchSlot<double>{});
+        sv->h_r64[par].assign(max_slots, BatchSlot<double>{});
+        sv->h_p32[par].assign(max_slots, BatchSlot<float>{});
+        sv->h_r32[par].assign(max_slots, BatchSlot<float>{});
+    }
+    sv->h_finp.assign(max_slots, BatchFin{});
+    sv->h_finr.assign(max_slots, BatchFin{});
+    pot3d_server *p = sv.get();
+    auto bail = [&](int code) {
+        pot3d_server_destroy(sv.release());
+        return code;
+    };
+    hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    for (int par = 0; par < 2 && e == hipSuccess; ++par) {
+        if (precision == POT3D_FP64) {
+            e = dalloc(&p->d_p64[par], max_slots);
+            if (e == hipSuccess) e = dalloc(&p->d_r64[par], max_slots);
+        } else {
+            e = dalloc(&p->d_p32[par], max_slots);
+            if (e == hipSuccess) e = dalloc(&p->d_r32[par], max_slots);
+        }
+    }
+    if (e == hipSuccess) e = dalloc(&p->d_finp, max_slots);
+    if (e == hipSuccess) e = dalloc(&p->d_finr, max_slots);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_status), max_slots * sizeof(DevScalars),
+                                           hipHostMallocDefault);
+    if (e != hipSuccess) {
+        sfail(nullptr, POT3D_EDEVICE, std::string("server allocation: ") + hipGetErrorString(e));
+        return bail(POT3D_EDEVICE);
+    }
+    if (upload_tables(p) != POT3D_OK) {
+        g_server_error = p->err;
+        return bail(POT3D_EDEVICE);
+    }
+    const int rc = precision == POT3D_FP64 ? capture_batched<double>(p, p->d_p64, p->d_r64)
+                                           : capture_batched<float>(p, p->d_p32, p->d_r32);
+    if (rc != POT3D_OK) {
+        g_server_error = p->err;
+        return bail(rc);
+    }
+    *out = sv.release();
+    return POT3D_OK;
+}
+
+int pot3d_server_submit(pot3d_server *sv, const double *r_faces, int nr, const double *t_faces, int nt,
+                        const double *p_faces, int np, const double *br, double tol, int maxit, long long *id)
+{
+    if (!sv) return sfail(nullptr, POT3D_EINVAL, "server is NULL");
+    if (!id || !br) return sfail(sv, POT3D_EINVAL, "br and id are required");
+    pot3d_ctx *dummy = nullptr;
+    if (validate_grid(r_faces, nr, t_faces, nt, p_faces, np, POT3D_UPPER_SOURCE_SURFACE, sv->precision, &dummy) !=
+        POT3D_OK)
+        return sfail(sv, POT3D_EINVAL, pot3d_last_error(nullptr));
+    if (!(tol >= 0.0) || !std::isfinite(tol) || maxit < 0) return sfail(sv, POT3D_EINVAL, "bad tol or maxit");
+    auto r = std::make_unique<Request>();
+    r->id = sv->next_id++;
+    r->nr = nr;
+    r->nt = nt;
+    r->np = np;
+    r->rf.assign(r_faces, r_faces + nr + 1);
+    r->tf.assign(t_faces, t_faces + nt + 1);
+    r->pf.assign(p_faces, p_faces + np + 1);
+    r->br.assign(br, br + (size_t)nt * np);
+    r->tol = tol;
+    r->maxit = maxit;
+    r->t_submit = sv->now();
+    *id = r->id;
+    sv->queue.push_back(r.get());
+    sv->requests[r->id] = std::move(r);
+    return POT3D_OK;
+}
+
+int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long *n_finished)
+{
+    if (!sv) return sfail(nullptr, POT3D_EINVAL, "server is NULL");
+    DeviceGuard guard(sv->device);
+    if (!guard.ok) return sfail(sv, POT3D_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = sv->stream;
+    bool changed = false;
+    // 1. slots whose current solve ended in the last replay
+    for (Slot &sl : sv->slots) {
+        if (!sl.active) continue;
+        const int q = (int)(&sl - sv->slots.data());
+        const DevScalars st = sv->h_status[q];
+        if (!st.done) continue;
+        changed = true;
+        if (sv->precision == POT3D_FP64) {
+            const int rc = retire(sv, sl, st, st.k, 1);
+            if (rc != POT3D_OK) return rc;
+        } else {
+            sl.total_inner += st.k;
+            sl.outer += 1;
+            if (st.status == POT3D_EBREAKDOWN) {
+                DevScalars out = st;
+                out.status = POT3D_EBREAKDOWN;
+                const int rc = retire(sv, sl, out, sl.total_inner, sl.outer);
+                if (rc != POT3D_OK) return rc;
+                continue;
+            }
+            SV_CALL(sv, sl.ctx, refined_correct(sl.ctx, s));
+            const int rc = refined_advance(sv, sl);
+            if (rc != POT3D_OK) return rc;
+        }
+    }
+    // 2. admissions
+    for (Slot &sl : sv->slots) {
+        if (sl.active || sv->queue.empty()) continue;
+        Request *r = sv->queue.front();
+        pot3d_ctx *c = nullptr;
+        int rc = acquire_context(sv, r, &c);
+        if (rc != POT3D_OK) {   // the request cannot run on this server
+            sv->queue.pop_front();
+            r->status = rc;
+            r->t_done = sv->now();
+            r->done = true;
+            ++sv->finished;
+            continue;
+        }
+        if (!c) break;   // wait for memory
+        sv->queue.pop_front();
+        changed = true;
+        rc = admit(sv, sl, r, c);
+        if (rc != POT3D_OK) return rc;
+    }
+    // 3. one replay of the batched iterations
+    int active = 0;
+    for (const Slot &sl : sv->slots) active += sl.active ? 1 : 0;
+    if (changed) {
+        const int rc = upload_tables(sv);
+        if (rc != POT3D_OK) return rc;
+    }
+    if (active > 0) {
+        SV_TRY(sv, hipGraphLaunch(sv->graph, s));
+        ++sv->replays;
+        for (Slot &sl : sv->slots) {
+            if (!sl.active) continue;
+            const int q = (int)(&sl - sv->slots.data());
+            sl.launches += 1;
+            DevScalars *src = sv->precision == POT3D_FP64 ? sl.ctx->sc : sl.ctx->sc32;
+            SV_TRY(sv, hipMemcpyAsync(&sv->h_status[q], src, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        }
+        SV_TRY(sv, hipStreamSynchronize(s));
+    }
+    if (n_active) *n_active = active;
+    if (n_queued) *n_queued = (int)sv->queue.size();
+    if (n_finished) *n_finished = sv->finished;
+    return POT3D_OK;
+}
+
+int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_request_info *info)
+{
+    if (!sv) return sfail(nullptr, POT3D_EINVAL, "server is NULL");
+    auto it = sv->requests.find(id);
+    if (it == sv->requests.end()) return sfail(sv, POT3D_EINVAL, "unknown request id");
+    Request *r = it->second.get();
+    if (info) {
+        info->id = r->id;
+        info->done = r->done ? 1 : 0;
+        info->status = r->status;
+        info->iters = r->iters;
+        info->outer = r->outer;
+        info->nr = r->nr;
+        info->nt = r->nt;
+        info->np = r->np;
+        info->relres_true = r->relres_true;
+        info->t_submit = r->t_submit;
+        info->t_admit = r->t_admit;
+        info->t_done = r->t_done;
+    }
+    if (r->done && phi) {
+        if (!r->phi.empty()) std::memcpy(phi, r->phi.data(), r->phi.size() * sizeof(double));
+        sv->requests.erase(it);
+    }
+    return POT3D_OK;
+}
+
+int pot3d_server_get_stats(const pot3d_server *sv, pot3d_server_stats *out)
+{
+    if (!sv || !out) return sfail(const_cast<pot3d_server *>(sv), POT3D_EINVAL, "server and out are required");
+    out->replays = sv->replays;
+    out->finished = sv->finished;
+    int active = 0;
+    for (const Slot &sl : sv->slots) active += sl.active ? 1 : 0;
+    out->active = active;
+    out->queued = (int)sv->queue.size();
+    out->cached_contexts = (int)sv->idle.size();
+    out->max_slots = sv->max_slots;
+    out->graph_iters = sv->graph_m;
+    out->used_bytes = (double)sv->used;
+    out->budget_bytes = (double)sv->budget;
+    return POT3D_OK;
+}
+
+void pot3d_server_destroy(pot3d_server *sv)
+{
+    if (!sv) return;
+    DeviceGuard guard(sv->device);
+    if (sv->stream) (void)hipStreamSynchronize(sv->stream);
+    for (Slot &sl : sv->slots)
+        if (sl.ctx) free_ctx(sl.ctx);
+    for (pot3d_ctx *c : sv->idle) free_ctx(c);
+    if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
+    void *bufs[] = {sv->d_p64[0], sv->d_p64[1], sv->d_r64[0], sv->d_r64[1], sv->d_p32[0], sv->d_p32[1],
+                    sv->d_r32[0], sv->d_r32[1], sv->d_finp, sv->d_finr};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (sv->h_status) (void)hipHostFree(sv->h_status);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+}
+
+}  // extern "C"

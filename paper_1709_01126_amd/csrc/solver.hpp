@@ -55,8 +55,8 @@ struct GridArgs {
     int ci;               // radial layers per workgroup chunk
     int nchunk, ntj, ntk; // chunks along r, tiles along theta and phi
     int nblocks;
-    int reverse;
-    long long npad;       // elements of each vector (nr * nt * pitch), for checked builds          // 1: walk the tiles in reverse order (see choose_launch)
+    int reverse;          // 1: walk the tiles in reverse order
+    long long npad;       // elements of each vector (nr * nt * pitch), for checked builds
     const RowCoef *rows;  // nr * nt
     const double *dphi;   // np: phi_f[k+1] - phi_f[k]
     const double *ih;     // np: 1 / (phi_{k+1} - phi_k), wrapping at k = np-1
@@ -82,6 +82,25 @@ struct StencilVecs {
     double *partial;  // [3][nblocks] per-workgroup partial sums
     int store_r;      // residual: 1 to store r, 0 to reduce only
     int ignore_done;  // 1: run even when sc->done is set
+};
+
+// One slot of a batched stencil launch (device-resident table).  `out` is the
+// pass's output vector: p_new for update-p, r for update-r (x is v.x).
+template <typename V>
+struct BatchSlot {
+    GridArgs g;
+    StencilVecs<V> v;
+    V *out;
+    int offset;   // first workgroup of the slot in the batched grid (multiple of 8)
+    int active;
+};
+
+// One slot of a batched finisher launch.
+struct BatchFin {
+    DevScalars *sc;
+    const double *partial;
+    int nb;
+    int active;
 };
 
 }  // namespace pot3d

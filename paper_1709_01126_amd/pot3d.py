@@ -24,7 +24,9 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
             "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement", "pot3d_destroy",
-            "pot3d_last_error", "pot3d_version")
+            "pot3d_last_error", "pot3d_version",
+            "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
+            "pot3d_server_get_stats", "pot3d_server_destroy", "pot3d_server_last_error")
 
 
 class pot3d_stats(ctypes.Structure):
@@ -34,6 +36,25 @@ class pot3d_stats(ctypes.Structure):
                 ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_p", ctypes.c_int),
                 ("tile_r", ctypes.c_int), ("chunk_p", ctypes.c_int), ("chunk_r", ctypes.c_int),
                 ("blocks_p", ctypes.c_int), ("blocks_r", ctypes.c_int)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class pot3d_request_info(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_longlong), ("done", ctypes.c_int), ("status", ctypes.c_int),
+                ("iters", ctypes.c_int), ("outer", ctypes.c_int), ("nr", ctypes.c_int), ("nt", ctypes.c_int),
+                ("np", ctypes.c_int), ("relres_true", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class pot3d_server_stats(ctypes.Structure):
+    _fields_ = [("replays", ctypes.c_longlong), ("finished", ctypes.c_longlong), ("active", ctypes.c_int),
+                ("queued", ctypes.c_int), ("cached_contexts", ctypes.c_int), ("max_slots", ctypes.c_int),
+                ("graph_iters", ctypes.c_int), ("used_bytes", ctypes.c_double), ("budget_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -78,6 +99,21 @@ def load(path: str = LIB_PATH):
     lib.pot3d_last_error.restype = ctypes.c_char_p
     lib.pot3d_version.argtypes = []
     lib.pot3d_version.restype = ctypes.c_char_p
+    ll = ctypes.c_longlong
+    lib.pot3d_server_create.argtypes = [i, i, i, ctypes.c_double, ctypes.POINTER(vp)]
+    lib.pot3d_server_create.restype = i
+    lib.pot3d_server_submit.argtypes = [vp, d, i, d, i, d, i, d, ctypes.c_double, i, ctypes.POINTER(ll)]
+    lib.pot3d_server_submit.restype = i
+    lib.pot3d_server_step.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(ll)]
+    lib.pot3d_server_step.restype = i
+    lib.pot3d_server_result.argtypes = [vp, ll, d, ctypes.POINTER(pot3d_request_info)]
+    lib.pot3d_server_result.restype = i
+    lib.pot3d_server_get_stats.argtypes = [vp, ctypes.POINTER(pot3d_server_stats)]
+    lib.pot3d_server_get_stats.restype = i
+    lib.pot3d_server_destroy.argtypes = [vp]
+    lib.pot3d_server_destroy.restype = None
+    lib.pot3d_server_last_error.argtypes = [vp]
+    lib.pot3d_server_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -248,6 +284,116 @@ class Solver:
         if self.ctx:
             pot3d_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def pot3d_server_last_error(sv=None) -> str:
+    return load().pot3d_server_last_error(sv).decode()
+
+
+def pot3d_server_create(device=0, precision=FP64, max_slots=8, hbm_budget_bytes=0.0):
+    """Returns (status, server handle or None)."""
+    out = ctypes.c_void_p(None)
+    st = load().pot3d_server_create(int(device), int(precision), int(max_slots), float(hbm_budget_bytes),
+                                    ctypes.byref(out))
+    return st, (out.value if st == OK else None)
+
+
+def pot3d_server_submit(sv, r_faces, t_faces, p_faces, br, tol, maxit):
+    """Returns (status, request id)."""
+    rf, tf, pf, br = _f64(r_faces), _f64(t_faces), _f64(p_faces), _f64(br)
+    rid = ctypes.c_longlong(0)
+    st = load().pot3d_server_submit(sv, _dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1, _dp(br),
+                                    float(tol), int(maxit), ctypes.byref(rid))
+    return st, rid.value
+
+
+def pot3d_server_step(sv):
+    """Returns (status, active, queued, finished)."""
+    a, q, f = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_longlong(0)
+    st = load().pot3d_server_step(sv, ctypes.byref(a), ctypes.byref(q), ctypes.byref(f))
+    return st, a.value, q.value, f.value
+
+
+def pot3d_server_result(sv, rid, phi_out=None):
+    """phi_out: None (query only) or a float64 array of N.  Returns (status, info dict)."""
+    info = pot3d_request_info()
+    st = load().pot3d_server_result(sv, int(rid), _dp(phi_out), ctypes.byref(info))
+    return st, info.as_dict()
+
+
+def pot3d_server_get_stats(sv):
+    s = pot3d_server_stats()
+    st = load().pot3d_server_get_stats(sv, ctypes.byref(s))
+    return st, s.as_dict()
+
+
+def pot3d_server_destroy(sv):
+    if sv:
+        load().pot3d_server_destroy(sv)
+
+
+class Server:
+    """Owns one continuous-batching server; raises Pot3dError on errors of the calls."""
+
+    def __init__(self, precision=FP64, max_slots=8, hbm_budget_bytes=0.0, device=0):
+        st, sv = pot3d_server_create(device, precision, max_slots, hbm_budget_bytes)
+        if st != OK:
+            raise Pot3dError(st, pot3d_server_last_error(None))
+        self.sv = sv
+        self.shapes = {}
+
+    def _check(self, st):
+        if st != OK:
+            raise Pot3dError(st, pot3d_server_last_error(self.sv))
+
+    def submit(self, r_faces, t_faces, p_faces, br, tol, maxit):
+        st, rid = pot3d_server_submit(self.sv, r_faces, t_faces, p_faces, br, tol, maxit)
+        self._check(st)
+        self.shapes[rid] = (len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1)
+        return rid
+
+    def step(self):
+        """One step; returns (active, queued, finished)."""
+        st, a, q, f = pot3d_server_step(self.sv)
+        self._check(st)
+        return a, q, f
+
+    def info(self, rid):
+        st, info = pot3d_server_result(self.sv, rid, None)
+        self._check(st)
+        return info
+
+    def take(self, rid):
+        """Phi and info of a finished request (which the server then forgets)."""
+        phi = np.empty(self.shapes[rid])
+        st, info = pot3d_server_result(self.sv, rid, phi)
+        self._check(st)
+        if not info["done"]:
+            raise Pot3dError(EINVAL, f"request {rid} is not done")
+        del self.shapes[rid]
+        return phi, info
+
+    def stats(self):
+        st, s = pot3d_server_get_stats(self.sv)
+        self._check(st)
+        return s
+
+    def close(self):
+        if self.sv:
+            pot3d_server_destroy(self.sv)
+            self.sv = None
 
     def __del__(self):
         try:

@@ -109,3 +109,21 @@ def test_null_arguments():
     assert P.pot3d_get_stats(None)[0] == P.EINVAL
     assert P.pot3d_time_kernels(None, 3)[0] == P.EINVAL
     P.pot3d_destroy(None)
+
+
+def test_server_rejects_invalid_arguments():
+    lib = P.load()
+    out = ctypes.c_void_p(None)
+    assert lib.pot3d_server_create(0, 0, 4, 0.0, None) == P.EINVAL
+    for prec, slots, budget in [(9, 4, 0.0), (0, 0, 0.0), (0, 65, 0.0), (1, 4, -1.0), (0, 4, math.inf),
+                                (0, 4, math.nan)]:
+        assert lib.pot3d_server_create(0, prec, slots, budget, ctypes.byref(out)) == P.EINVAL, (prec, slots, budget)
+        assert out.value is None
+        assert P.pot3d_server_last_error(None) != ""
+    rf, tf, pf = good_faces()
+    br = np.zeros(6 * 8)
+    assert P.pot3d_server_submit(None, rf, tf, pf, br, 1e-10, 10)[0] == P.EINVAL
+    assert P.pot3d_server_step(None)[0] == P.EINVAL
+    assert P.pot3d_server_result(None, 1)[0] == P.EINVAL
+    assert P.pot3d_server_get_stats(None)[0] == P.EINVAL
+    P.pot3d_server_destroy(None)
