@@ -135,6 +135,145 @@ def cpu_baseline(w, faces, br, budget_s: float):
                       f"{dt:.1f} s, OpenMP threads={cores}; assembly excluded"}
 
 
+def percentile(xs, q):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def fifo_latencies(arrivals, service):
+    """Latencies of a single FIFO server that runs one request at a time."""
+    free, out = 0.0, []
+    for a, s in zip(arrivals, service):
+        start = max(a, free)
+        free = start + s
+        out.append(free - a)
+    return out
+
+
+def serve_trace(server, reqs, arrivals, log):
+    """Submit each request at its arrival time (host clock, relative to the
+    first step) and step the server until all are done.  Returns per-request
+    (latency s, iters, status, relres_true) and the makespan."""
+    k = len(reqs)
+    ids = [None] * k
+    done = [None] * k
+    nxt = 0
+    t0 = time.perf_counter()
+    t_sub = [0.0] * k
+    while any(d is None for d in done):
+        now = time.perf_counter() - t0
+        while nxt < k and arrivals[nxt] <= now:
+            w, faces, br = reqs[nxt]
+            ids[nxt] = server.submit(*faces, br, w.tol, 1_000_000)
+            t_sub[nxt] = server.info(ids[nxt])["t_submit"]
+            nxt += 1
+        active, queued, _ = server.step()
+        for q in range(nxt):
+            if done[q] is None:
+                info = server.info(ids[q])
+                if info["done"]:
+                    server.take(ids[q])
+                    done[q] = (info["t_done"] - t_sub[q], info["iters"], info["status"], info["relres_true"])
+                    log(f"[serve]   request {q} {info['nr']}x{info['nt']}x{info['np']} done: "
+                        f"latency {done[q][0]:.3f} s, iters {info['iters']}")
+        if active == 0 and queued == 0 and nxt < k:
+            time.sleep(max(0.0, arrivals[nxt] - (time.perf_counter() - t0)))
+    return done, time.perf_counter() - t0
+
+
+def serve_main(args):
+    """Continuous-batching serving on the mixed-size request trace."""
+    import numpy as np
+    import torch  # noqa: F401  (initialises the device the way the tests do)
+
+    from paper_1709_01126_amd import FP32_REFINED, FP64, Server, Solver
+    from workloads import configs
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    k = args.serve_requests
+    reqs = []
+    for q in range(k):
+        w = configs.serve_request(q)
+        faces = w.faces()
+        reqs.append((w, faces, w.br(faces)))
+    sizes = sorted({(w.nr, w.nt, w.np) for w, _, _ in reqs})
+    log(f"[serve] {k} requests, sizes {sizes}, {args.serve_slots} slots")
+    arrivals_cfg = configs.poisson_arrivals(k, args.serve_rate, seed=17)
+    result = {"metric": "serving: solves/s and p50/p99 latency, continuous batching vs sequential solves",
+              "unit": "solves/s", "n_gpus": 1, "data": "synthetic", "higher_is_better": True,
+              "config": {"workload": f"serve trace of {k} requests: sizes uniform over {list(configs.SERVE_SIZES)}, "
+                                     f"50..500 bipoles, tol 1e-9", "slots": args.serve_slots,
+                         "rate_per_s": args.serve_rate,
+                         "cache_budget_bytes": args.serve_cache_budget if args.serve_cache_budget is not None
+                         else 256 * 2 ** 20},
+              "modes": {}}
+    for name, prec in (("fp64", FP64), ("fp32_refined", FP32_REFINED)):
+        # sequential: one solve at a time through pot3d_solve, contexts cached per grid
+        solvers = {}
+        for w, faces, br in reqs:
+            key = (w.nr, w.nt, w.np)
+            if key not in solvers:
+                solvers[key] = Solver(*faces, precision=prec)
+                solvers[key].solve(br, w.tol, 1_000_000)   # warm-up
+        service, seq_res = [], []
+        for q, (w, faces, br) in enumerate(reqs):
+            t = time.perf_counter()
+            _, st, it, rr = solvers[(w.nr, w.nt, w.np)].solve(br, w.tol, 1_000_000)
+            service.append(time.perf_counter() - t)
+            seq_res.append((it, st, rr))
+        for sv in solvers.values():
+            sv.close()
+        seq_rate = k / sum(service)
+        log(f"[serve] {name} sequential: {seq_rate:.3f} solves/s, mean solve {np.mean(service):.3f} s")
+        mode = {"sequential": {"solves_per_s": round(seq_rate, 4), "mean_solve_s": round(float(np.mean(service)), 4),
+                               "max_relres_true": max(r[2] for r in seq_res)}}
+        with Server(precision=prec, max_slots=args.serve_slots) as server:
+            if args.serve_cache_budget is not None:
+                server.set_cache_budget(args.serve_cache_budget)
+            # warm-up: one request per size, so each grid has a cached context
+            warm = []
+            for key in sizes:
+                w, faces, br = next(r for r in reqs if (r[0].nr, r[0].nt, r[0].np) == key)
+                warm.append((w, faces, br))
+            serve_trace(server, warm, [0.0] * len(warm), lambda m: None)
+            runs = [("saturation", [0.0] * k), (f"poisson_{args.serve_rate:g}", list(arrivals_cfg))]
+            for label, arr in runs:
+                log(f"[serve] {name} server, arrivals: {label}")
+                res, span = serve_trace(server, reqs, arr, log)
+                lat = [r[0] for r in res]
+                seq_lat = fifo_latencies(arr, service)
+                mode[label] = {
+                    "server": {"solves_per_s": round(k / span, 4), "p50_s": round(percentile(lat, 50), 4),
+                               "p99_s": round(percentile(lat, 99), 4),
+                               "max_relres_true": max(r[3] for r in res),
+                               "status_ok": sum(r[2] == 0 for r in res)},
+                    "sequential_fifo": {"p50_s": round(percentile(seq_lat, 50), 4),
+                                        "p99_s": round(percentile(seq_lat, 99), 4)},
+                    "iters_equal_sequential": all(r[1] == s[0] for r, s in zip(res, seq_res)),
+                }
+                log(f"[serve] {name} {label}: {json.dumps(mode[label])}")
+            # a sustainable rate: 70% of the measured server throughput
+            lam = 0.7 * mode["saturation"]["server"]["solves_per_s"]
+            arr = list(configs.poisson_arrivals(k, lam, seed=19))
+            log(f"[serve] {name} server, arrivals: poisson at {lam:.3f}/s (70% of saturation)")
+            res, span = serve_trace(server, reqs, arr, log)
+            lat = [r[0] for r in res]
+            seq_lat = fifo_latencies(arr, service)
+            mode["poisson_sustainable"] = {
+                "rate_per_s": round(lam, 4),
+                "server": {"p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4)},
+                "sequential_fifo": {"p50_s": round(percentile(seq_lat, 50), 4),
+                                    "p99_s": round(percentile(seq_lat, 99), 4)},
+            }
+            mode["server_stats"] = server.stats()
+        result["modes"][name] = mode
+    result["value"] = result["modes"]["fp64"]["saturation"]["server"]["solves_per_s"]
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +289,14 @@ def main():
     ap.add_argument("--profile-kernels", action="store_true",
                     help="short run for hardware counters: a few iterations, the two stencil kernels "
                          "--kernel-reps times each, and one device copy of N doubles (counter calibration)")
+    ap.add_argument("--serve", action="store_true",
+                    help="continuous-batching serving benchmark on the mixed-size request trace (own JSON line)")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-cache-budget", type=float, default=None,
+                    help="bytes streamed per iteration by the batch (server default: 256 MiB; 0 = no limit)")
+    ap.add_argument("--no-refined", action="store_true", help="skip the FP32-refined solves of the default run")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, *args.summarize_pmc)
@@ -159,10 +306,14 @@ def main():
               "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.serve:
+        serve_main(args)
+        return
+
     import numpy as np
     import torch
 
-    from paper_1709_01126_amd import Solver, pot3d
+    from paper_1709_01126_amd import FP32_REFINED, Solver, pot3d
     from workloads import WORKLOADS
 
     w = WORKLOADS[args.workload]
@@ -259,6 +410,28 @@ def main():
         "relres_true": stats["relres_true"],
         "phi_l2": phi_norm,
     }
+    if not args.no_refined:
+        # FP32-refined solves of the same problem to the same FP64 residual
+        phi64 = d_phi.clone()
+        solver.close()
+        solver = Solver(*faces, precision=FP32_REFINED, device=0)
+        st, it, rr = solver.solve_device(d_br, d_phi, w.tol, maxit)
+        print(f"[bench] refined warmup: status={st} inner iters={it} true_relres={rr:.3e}", file=sys.stderr,
+              flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(args.steps):
+            st, it, rr = solver.solve_device(d_br, d_phi, w.tol, maxit)
+        torch.cuda.synchronize()
+        t_ref = (time.perf_counter() - t0) / args.steps
+        rs = solver.stats()
+        diff = float(torch.max(torch.abs(d_phi - phi64)).item() / torch.max(torch.abs(phi64)).item())
+        result["fp32_refined"] = {"solve_s": round(t_ref, 4), "speedup_vs_fp64": round(result["fp64_solve_s"] / t_ref, 3),
+                                  "inner_iters": it, "outer": rs["outer"], "relres_true": rr,
+                                  "status": pot3d.STATUS_NAMES.get(st, st),
+                                  "max_rel_diff_vs_fp64_gpu": diff}
+        print(f"[bench] refined: {t_ref:.3f} s/solve ({it} inner iters, {rs['outer']} outer)", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, faces, br, args.cpu_budget)

@@ -125,7 +125,7 @@ int pot3d_solve(pot3d_ctx *ctx, const double *br, double tol, int maxit,
  * All work is ordered on `stream`; the call returns after the solve has
  * finished (it waits on the stream for the convergence flag).
  * In POT3D_FP32_REFINED contexts the outer loop recomputes r = b - A Phi in
- * FP64, solves A e = r with FP32 PCG to inner_tol (1e-5), and adds e to Phi in
+ * FP64, solves A e = r with FP32 PCG to inner_tol (1e-4), and adds e to Phi in
  * FP64.  It repeats until the FP64 true residual is <= tol.
  */
 int pot3d_solve_device(pot3d_ctx *ctx, const double *d_br, const double *d_phi0, double *d_phi,
@@ -167,7 +167,7 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
 
 /*
  * FP32-refined contexts only: tolerance of each inner FP32 solve, relative to
- * its right-hand side ||r||, in (0, 1) (default 1e-5), and the most outer
+ * its right-hand side ||r||, in (0, 1) (default 1e-4), and the most outer
  * defect-correction cycles (default 50).  POT3D_EINVAL otherwise.
  */
 int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer);
@@ -189,8 +189,9 @@ const char *pot3d_version(void);
  * grid with its own surface map Br, share the GPU.  Requests queue on the
  * host.  Each pot3d_server_step:
  *   1. retires the solves that ended in the previous step;
- *   2. admits queued requests, in order, while a slot is free and their
- *      device memory fits the budget;
+ *   2. admits queued requests, in order, while a slot is free, their device
+ *      memory fits the budget, and the bytes that the active solves stream
+ *      per iteration stay within the cache budget (or no solve is active);
  *   3. advances every active solve by a fixed number of PCG iterations
  *      (16), all in one replay of one captured HIP graph.
  * As in Sec. 3.1, the vectors of a solve stay in device memory from
@@ -261,6 +262,16 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
  * is forgotten; later calls with its id return POT3D_EINVAL.
  */
 int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_request_info *info);
+
+/*
+ * Streaming budget of the batch: a request joins the active solves only if
+ * the bytes they all stream per iteration (32 per cell in FP64, 16 in refined
+ * mode) stay within `bytes`, or if none is active.  Default 256 MiB, the
+ * memory-side cache of the device: solves that run from it alone are not
+ * slowed by batching, and bandwidth-bound ones run alone, since batching
+ * cannot speed them up.  0 removes the limit.
+ */
+int pot3d_server_set_cache_budget(pot3d_server *sv, double bytes);
 
 int pot3d_server_get_stats(const pot3d_server *sv, pot3d_server_stats *out);
 

@@ -183,22 +183,40 @@ int resident_blocks(const pot3d_ctx *c, int mode, int tile)
     return std::max(1, per_cu) * std::max(1, c->num_cu);
 }
 
-// Default shapes (measured on MI355X at 151 x 301 x 601): both iteration
-// passes on the LDS-plane kernel, with radial chunks sized so one launch fills
-// at most half of the resident workgroup slots: fewer, longer chunks repeat
-// fewer boundary layers, and a single wave of workgroups leaves no tail.
+// Default shapes (measured on MI355X at 151 x 301 x 601).  FP64: both
+// iteration passes on the 8-row LDS-plane kernel, with radial chunks sized so
+// one launch fills at most half of the resident workgroup slots: fewer, longer
+// chunks repeat fewer boundary layers, and a single wave of workgroups leaves
+// no tail.  FP32 passes move half the bytes per cell, so a workgroup keeps
+// fewer bytes in flight and more of them are needed: the p update runs
+// 16-row tiles at about 6 workgroups per CU, and the r/x update runs on the
+// two-row wavefront kernel with about 4096 workgroups.
 // POT3D_TILE[_P|_R] and POT3D_TARGET_BLOCKS[_P|_R] override.
+void default_tiles(int precision, int *tile_p, int *tile_r)
+{
+    const bool fp32 = precision == POT3D_FP32_REFINED;
+    const int all = valid_tile(env_int("POT3D_TILE", 0), 0);
+    const int dflt_p = fp32 ? kTileMarch16 : kTileMarch8;
+    const int dflt_r = fp32 ? kTileWave2 : kTileMarch8;
+    *tile_p = valid_tile(env_int("POT3D_TILE_P", all ? all : dflt_p), dflt_p);
+    *tile_r = valid_tile(env_int("POT3D_TILE_R", all ? all : dflt_r), dflt_r);
+}
+
 void choose_launch(pot3d_ctx *c)
 {
+    const bool fp32 = c->precision == POT3D_FP32_REFINED;
     const int all = valid_tile(env_int("POT3D_TILE", 0), 0);
-    c->tile_p = valid_tile(env_int("POT3D_TILE_P", all ? all : kTileMarch8), kTileMarch8);
-    c->tile_r = valid_tile(env_int("POT3D_TILE_R", all ? all : kTileMarch8), kTileMarch8);
+    default_tiles(c->precision, &c->tile_p, &c->tile_r);
     c->tile_o = all ? all : kTileWave2;
-    if (c->serving) c->tile_p = c->tile_r = kTileMarch8;   // the batched kernels' tile
     const int tb = env_int("POT3D_TARGET_BLOCKS", 0);
     const int tp = env_int("POT3D_TARGET_BLOCKS_P", tb), tr = env_int("POT3D_TARGET_BLOCKS_R", tb);
-    c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : resident_blocks(c, kUpdateP, c->tile_p) / 2);
-    c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : resident_blocks(c, kUpdateR, c->tile_r) / 2);
+    auto dflt_target = [&](int mode, int tile) {
+        if (tile_is_wave(tile)) return 4096;
+        if (fp32) return 6 * c->num_cu;
+        return resident_blocks(c, mode, tile) / 2;
+    };
+    c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : dflt_target(kUpdateP, c->tile_p));
+    c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : dflt_target(kUpdateR, c->tile_r));
     c->grid_o = make_grid(c, c->tile_o, tb > 0 ? tb : 2048);
     // The r/x update walks the tiles in the opposite order to the p update, so
     // each pass starts on the tiles the previous pass touched last, while their
@@ -355,7 +373,14 @@ int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMem
     const size_t nrows = (size_t)c->nr * c->nt;
     c->have_solution = false;
     HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, c->bplane, s));
-    if (phi0) HIP_TRY(c, copy_rows(c->x, pitchb, phi0, rowb, rowb, nrows, kind_in, s));
+    if (phi0 && kind_in == hipMemcpyHostToDevice && c->pitch != c->np) {
+        // one contiguous host copy into r (free until the solve starts), then
+        // the padded layout on the device
+        HIP_TRY(c, hipMemcpyAsync(c->r, phi0, (size_t)c->n * sizeof(double), kind_in, s));
+        HIP_TRY(c, launch_repack(c->r, c->x, (long long)nrows, c->np, c->pitch, false, s));
+    } else if (phi0) {
+        HIP_TRY(c, copy_rows(c->x, pitchb, phi0, rowb, rowb, nrows, kind_in, s));
+    }
     else HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
     return POT3D_OK;
 }
@@ -506,7 +531,13 @@ int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStrea
     HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, tv, s));
     HIP_TRY(c, launch_finish(kFinTrue, c->sc, c->partial, c->grid_o.nblocks, s));
     HIP_TRY(c, launch_poles(c->x, c->dphi, c->nr, c->nt, c->np, c->pitch, kTwoPi, c->poles, s));
-    HIP_TRY(c, copy_rows(phi_out, rowb, c->x, pitchb, rowb, nrows, kind_out, s));
+    if (kind_out == hipMemcpyDeviceToHost && c->pitch != c->np) {
+        // packed on the device into r (no longer needed), then one contiguous copy
+        HIP_TRY(c, launch_repack(c->x, c->r, (long long)nrows, c->np, c->pitch, true, s));
+        HIP_TRY(c, hipMemcpyAsync(phi_out, c->r, (size_t)c->n * sizeof(double), kind_out, s));
+    } else {
+        HIP_TRY(c, copy_rows(phi_out, rowb, c->x, pitchb, rowb, nrows, kind_out, s));
+    }
     HIP_TRY(c, hipMemcpyAsync(&c->h_sc[0], c->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipEventRecord(c->ev_t1, s));
     HIP_TRY(c, hipStreamSynchronize(s));

@@ -50,10 +50,10 @@ struct pot3d_ctx {
     float *r32 = nullptr, *p32[2] = {nullptr, nullptr}, *e32 = nullptr;
     DevScalars *sc32 = nullptr;
     hipGraphExec_t graph32 = nullptr;
-    double inner_tol = 1e-5;
+    double inner_tol = 1e-4;
     int max_outer = 50;
 
-    bool serving = false;         // a batching-server slot (launch shapes fixed to the batched kernels)
+    bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;
     pot3d_stats stats{};
     std::string err;
@@ -88,10 +88,13 @@ struct DeviceGuard {
     }
 };
 
+// Tile shapes of the two iteration passes for a precision (the defaults, or
+// the POT3D_TILE[_P|_R] overrides); every context of the process uses them.
+void default_tiles(int precision, int *tile_p, int *tile_r);
 int validate_grid(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,
                   int precision, pot3d_ctx **out);
 // Allocate a context on `device` (tables, vectors, graphs).  serving = true:
-// launch shapes fixed to the batched kernels' tile and no graph capture.
+// no graph capture (the server's batched graph iterates it).
 int create_context(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,
                    int precision, int device, bool serving, pot3d_ctx **out);
 void free_ctx(pot3d_ctx *c);

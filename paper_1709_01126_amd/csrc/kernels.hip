@@ -55,6 +55,38 @@ template <typename V> __device__ __forceinline__ V vfma(V a, V b, V c);
 template <> __device__ __forceinline__ double vfma<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 template <> __device__ __forceinline__ float vfma<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Pointer to global memory, typed as such.
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ GPtr<T> to_global(T *p)
+{
+    return (GPtr<T>)p;
+}
+
+// Pointer to memory that no kernel writes while this one runs (row tables,
+// the scalar block): uniform loads through it become scalar loads.
+template <typename T>
+using CPtr = __attribute__((address_space(4))) T *;
+template <typename T>
+__device__ __forceinline__ CPtr<T> to_const(T *p)
+{
+    return (CPtr<T>)p;
+}
+
+__device__ __forceinline__ RowCoef load_row(CPtr<const RowCoef> rows, long long idx)
+{
+    RowCoef r;
+    r.rm = rows[idx].rm;
+    r.rp = rows[idx].rp;
+    r.tm = rows[idx].tm;
+    r.tp = rows[idx].tp;
+    r.s = rows[idx].s;
+    r.pq = rows[idx].pq;
+    r.pad0 = r.pad1 = 0.0;
+    return r;
+}
+
 // Diagonal of A at one point (the Jacobi preconditioner).
 template <typename V>
 __device__ __forceinline__ V diag_at(const RowCoef &rc, V dph, V ihm, V ihk)
@@ -76,7 +108,18 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
     __shared__ V lds[3][TJ + 2][TK + 2];
     __shared__ double red[kWaves][3];
 
-    if (!v.ignore_done && v.sc->done) return;   // uniform over the workgroup
+    const CPtr<const DevScalars> csc = to_const(v.sc);
+    const CPtr<const RowCoef> crows = to_const(rows);
+    if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
+
+    // Element accesses go through global-address-space pointers.  A batched
+    // launch reads its pointers from the slot table, and the compiler would
+    // otherwise use flat accesses there, which share a wait counter with the
+    // LDS traffic of the plane pipeline.
+    const GPtr<const V> gin = to_global(vin), gpold = to_global(vpold);
+    const GPtr<V> gout = to_global(vout), gout2 = to_global(vout2);
+    const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih), gbp = to_global(v.bplane);
+    const GPtr<double> gpart = to_global(v.partial);
 
     // Workgroup -> tile.  Hardware hands consecutive workgroup ids to the 8
     // XCDs in turn; renumber so that each XCD works on a contiguous range of
@@ -106,9 +149,9 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
     // which the right halo column holds.
     const int kp_col = (k == np - 1) ? TK + 1 : lane + 2;
 
-    const V dph = kval ? (V)g.dphi[CHK(kc, np)] : V(0);
-    const V ihm = kval ? (V)g.ih[CHK(kc == 0 ? np - 1 : kc - 1, np)] : V(0);
-    const V ihk = kval ? (V)g.ih[CHK(kc, np)] : V(0);
+    const V dph = kval ? (V)gdphi[CHK(kc, np)] : V(0);
+    const V ihm = kval ? (V)gih[CHK(kc == 0 ? np - 1 : kc - 1, np)] : V(0);
+    const V ihk = kval ? (V)gih[CHK(kc, np)] : V(0);
 
     // Halo ring of the tile in one layer: wave 0 the row below (j0-1), wave 1
     // the row above (j0+TJ), wave 2 the left and right columns (wrapped in phi).
@@ -132,14 +175,14 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
     const V mh = hval ? V(1) : V(0);
     V hdph = 0, hihm = 0, hihk = 0;
     if (MODE == kUpdateP) {
-        hdph = (V)g.dphi[CHK(hk, np)];
-        hihm = (V)g.ih[CHK(hk == 0 ? np - 1 : hk - 1, np)];
-        hihk = (V)g.ih[CHK(hk, np)];
+        hdph = (V)gdphi[CHK(hk, np)];
+        hihm = (V)gih[CHK(hk == 0 ? np - 1 : hk - 1, np)];
+        hihk = (V)gih[CHK(hk, np)];
     }
 
     V beta = 0, alpha = 0;
-    if (MODE == kUpdateP) beta = (V)v.sc->beta;
-    if (MODE == kUpdateR) alpha = (V)v.sc->alpha;
+    if (MODE == kUpdateP) beta = (V)csc->beta;
+    if (MODE == kUpdateR) alpha = (V)csc->alpha;
 
     auto offs = [&](int ip, int j, int kk) -> long long {
         return (long long)ip * g.plane + (long long)j * g.pitch + kk;
@@ -166,10 +209,10 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
         for (int m = 0; m < M; ++m) {
             const int jc = min(j0 + w + kWaves * m, nt - 1);
             const long long o = offs(ip, jc, kc);
-            ra[m] = vin[CHK(o, g.npad)];
+            ra[m] = gin[CHK(o, g.npad)];
             if constexpr (MODE == kUpdateP) {
-                rb[m] = vpold[CHK(o, g.npad)];
-                rcs[m] = rows[CHK(ip * nt + jc, nr * nt)];
+                rb[m] = gpold[CHK(o, g.npad)];
+                rcs[m] = load_row(crows, CHK(ip * nt + jc, nr * nt));
             } else {
                 rb[m] = 0;
             }
@@ -178,10 +221,10 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
         RowCoef hrc{};
         if (to_lds) {
             const long long o = offs(ip, hjc, hk);
-            ha = vin[CHK(o, g.npad)];
+            ha = gin[CHK(o, g.npad)];
             if constexpr (MODE == kUpdateP) {
-                hb = vpold[CHK(o, g.npad)];
-                hrc = rows[CHK(ip * nt + hjc, nr * nt)];
+                hb = gpold[CHK(o, g.npad)];
+                hrc = load_row(crows, CHK(ip * nt + hjc, nr * nt));
             }
         }
 #pragma unroll
@@ -192,7 +235,7 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
             const V val = eval(ra[m], rb[m], rcs[m], dph, ihm, ihk, mrow);
             dst[m] = val;
             if constexpr (MODE == kUpdateP) {
-                if (store && kval && j < nt) vout[CHK(offs(ip, j, k), g.npad)] = val;
+                if (store && kval && j < nt) gout[CHK(offs(ip, j, k), g.npad)] = val;
             }
             if (to_lds) lds[slot][row + 1][lane + 1] = val;
         }
@@ -211,11 +254,11 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int jc = min(j0 + w + kWaves * m, nt - 1);
-            rc[m] = rows[CHK(i * nt + jc, nr * nt)];
+            rc[m] = load_row(crows, CHK(i * nt + jc, nr * nt));
             if constexpr (MODE == kUpdateR) {
                 const long long o = CHK(offs(i, jc, kc), g.npad);
-                rv[m] = vout[o];
-                xv[m] = vout2[o];
+                rv[m] = gout[o];
+                xv[m] = gout2[o];
             }
         }
         produce(i + 1, i + 1 < nr, (i + 1) % 3, q2, true, MODE == kUpdateP && i + 1 < i1);
@@ -244,12 +287,12 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
             const V ap = vfma<V>(dph, t, (V)r_.pq * u);
             const long long idx = on ? CHK(offs(i, j, k), g.npad) : 0;
             if constexpr (MODE == kApply) {
-                if (on) vout[idx] = ap;
+                if (on) gout[idx] = ap;
             } else if constexpr (MODE == kResidual) {
                 if (on) {
-                    const double bval = (i == 0) ? v.bplane[CHK((long long)j * g.pitch + k, (long long)nt * g.pitch)] : 0.0;
+                    const double bval = (i == 0) ? gbp[CHK((long long)j * g.pitch + k, (long long)nt * g.pitch)] : 0.0;
                     const V res = (V)(bval - (double)ap);
-                    if (v.store_r) vout[idx] = res;
+                    if (v.store_r) gout[idx] = res;
                     const V z = res / diag_at<V>(r_, dph, ihm, ihk);
                     acc0 += (double)res * (double)z;
                     acc1 += (double)res * (double)res;
@@ -260,8 +303,8 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
             } else {  // kUpdateR
                 if (on) {
                     const V rn = vfma<V>(-alpha, ap, rv[m]);
-                    vout[idx] = rn;
-                    vout2[idx] = vfma<V>(alpha, pc, xv[m]);
+                    gout[idx] = rn;
+                    gout2[idx] = vfma<V>(alpha, pc, xv[m]);
                     const V z = rn / diag_at<V>(r_, dph, ihm, ihk);
                     acc0 += (double)rn * (double)z;
                     acc1 += (double)rn * (double)rn;
@@ -296,9 +339,9 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
                 s1 += red[q][1];
                 s2 += red[q][2];
             }
-            v.partial[CHK(b, g.nblocks)] = s0;
-            v.partial[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
-            v.partial[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
+            gpart[CHK(b, g.nblocks)] = s0;
+            gpart[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
+            gpart[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
     }
 }
@@ -311,6 +354,18 @@ stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, co
     march_body<TJ, MODE, V>(g, v, rows, vin, vpold, vout, vout2, blockIdx.x);
 }
 
+// Index of the slot that owns workgroup bid of a batched launch, or -1.
+template <typename V>
+__device__ __forceinline__ int batch_slot(const BatchSlot<V> *__restrict__ slots, int nslots, int bid)
+{
+    int s = -1;
+    for (int q = 0; q < nslots; ++q) {
+        const BatchSlot<V> &sl = slots[q];
+        if (sl.active && bid >= sl.offset && bid < sl.offset + sl.g.nblocks) s = q;
+    }
+    return s;
+}
+
 // Batched pass: one launch covers every active slot of a slot table.  Slot q
 // owns workgroups [offset, offset + nblocks) of the grid (offsets are
 // multiples of 8, so the XCD-aware tile order inside a slot is unchanged), and
@@ -320,13 +375,9 @@ __global__ void __launch_bounds__(kThreads)
 stencil_march_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 {
     const int bid = blockIdx.x;
-    int s = -1;
-    for (int q = 0; q < nslots; ++q) {
-        const BatchSlot<V> &sl = slots[q];
-        if (sl.active && bid >= sl.offset && bid < sl.offset + sl.g.nblocks) s = q;
-    }
+    const int s = batch_slot(slots, nslots, bid);
     if (s < 0) return;
-    const BatchSlot<V> &sl = slots[s];
+    const BatchSlot<V> sl = slots[s];
     march_body<TJ, MODE, V>(sl.g, sl.v, sl.g.rows, sl.v.in, sl.v.pold, sl.out, sl.v.x, bid - sl.offset);
 }
 
@@ -347,9 +398,12 @@ stencil_march_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 // trip per wavefront, and the wavefronts never wait for each other until the
 // final reduction.
 // ---------------------------------------------------------------------------
+// Two consecutive cells moved as one 16-byte (FP64) or 8-byte (FP32) access
+// (the compiler's own vector type, which loads and stores through
+// address-space-qualified pointers).
 template <typename V> struct Pair;
-template <> struct Pair<double> { using T = double2; };
-template <> struct Pair<float> { using T = float2; };
+template <> struct Pair<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct Pair<float> { typedef float T __attribute__((ext_vector_type(2))); };
 
 // Lane l receives the value of lane l-1 (lane 0 receives 0).
 __device__ __forceinline__ double lane_from_left(double v)
@@ -386,19 +440,24 @@ __device__ __forceinline__ float wave_uniform(float v)
 }
 
 template <int M, int MODE, typename V>
-__global__ void __launch_bounds__(kThreads)
-stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
-             const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
+__device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V> &v, const RowCoef *__restrict__ rows,
+                                          const V *__restrict__ vin, const V *__restrict__ vpold, V *__restrict__ vout,
+                                          V *__restrict__ vout2, const int b)
 {
     using P2 = typename Pair<V>::T;
     constexpr int SEG = 2 * kWave;   // azimuthal cells per task
     __shared__ double red[kWaves][3];
 
-    if (!v.ignore_done && v.sc->done) return;   // uniform over the workgroup
+    const CPtr<const DevScalars> csc = to_const(v.sc);
+    const CPtr<const RowCoef> crows = to_const(rows);
+    if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
+    const GPtr<const V> gin = to_global(vin), gpold = to_global(vpold);
+    const GPtr<V> gout = to_global(vout), gout2 = to_global(vout2);
+    const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih), gbp = to_global(v.bplane);
+    const GPtr<double> gpart = to_global(v.partial);
 
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int b = blockIdx.x;
     const int per = g.nblocks / kXcds;
     int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
     if (g.reverse) L = g.nblocks - 1 - L;
@@ -429,24 +488,24 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
 
         const int kc0 = v0 ? kb : 0, kc1 = v1 ? kb + 1 : 0;
         const V mv0 = v0 ? V(1) : V(0), mv1 = v1 ? V(1) : V(0);
-        const V dph0 = v0 ? (V)g.dphi[CHK(kc0, np)] : V(0), dph1 = v1 ? (V)g.dphi[CHK(kc1, np)] : V(0);
-        const V ihk0 = v0 ? (V)g.ih[CHK(kc0, np)] : V(0), ihk1 = v1 ? (V)g.ih[CHK(kc1, np)] : V(0);
-        const V ihm0 = v0 ? (V)g.ih[CHK(kc0 == 0 ? np - 1 : kc0 - 1, np)] : V(0), ihm1 = ihk0;
-        const V dphl = (V)g.dphi[CHK(kl, np)], ihml = (V)g.ih[CHK(kl == 0 ? np - 1 : kl - 1, np)], ihkl = (V)g.ih[CHK(kl, np)];
-        const V dphr = (V)g.dphi[CHK(kr, np)], ihmr = (V)g.ih[CHK(kr == 0 ? np - 1 : kr - 1, np)], ihkr = (V)g.ih[CHK(kr, np)];
-        const V beta = (MODE == kUpdateP) ? (V)v.sc->beta : V(0);
-        const V alpha = (MODE == kUpdateR) ? (V)v.sc->alpha : V(0);
+        const V dph0 = v0 ? (V)gdphi[CHK(kc0, np)] : V(0), dph1 = v1 ? (V)gdphi[CHK(kc1, np)] : V(0);
+        const V ihk0 = v0 ? (V)gih[CHK(kc0, np)] : V(0), ihk1 = v1 ? (V)gih[CHK(kc1, np)] : V(0);
+        const V ihm0 = v0 ? (V)gih[CHK(kc0 == 0 ? np - 1 : kc0 - 1, np)] : V(0), ihm1 = ihk0;
+        const V dphl = (V)gdphi[CHK(kl, np)], ihml = (V)gih[CHK(kl == 0 ? np - 1 : kl - 1, np)], ihkl = (V)gih[CHK(kl, np)];
+        const V dphr = (V)gdphi[CHK(kr, np)], ihmr = (V)gih[CHK(kr == 0 ? np - 1 : kr - 1, np)], ihkr = (V)gih[CHK(kr, np)];
+        const V beta = (MODE == kUpdateP) ? (V)csc->beta : V(0);
+        const V alpha = (MODE == kUpdateR) ? (V)csc->alpha : V(0);
 
         auto rowoff = [&](int ip, int j) -> long long { return (long long)ip * g.plane + (long long)j * g.pitch; };
-        auto ld2 = [&](const V *p, long long off) -> P2 { return *reinterpret_cast<const P2 *>(p + CHK(off, g.npad - 1)); };
+        auto ld2 = [&](GPtr<const V> p, long long off) -> P2 { return *(GPtr<const P2>)(p + CHK(off, g.npad - 1)); };
 
         // Raw loads of the operand on a row segment, and their evaluation.
         struct Raw { P2 a, b; };
         auto raw_row = [&](int ip, int j) -> Raw {
             const long long off = rowoff(ip, j) + kc;
             Raw q;
-            q.a = ld2(vin, off);
-            if constexpr (MODE == kUpdateP) q.b = ld2(vpold, off);
+            q.a = ld2(gin, off);
+            if constexpr (MODE == kUpdateP) q.b = ld2(gpold, off);
             return q;
         };
         // Evaluate a raw row segment with the row's coefficients (update-p: the
@@ -473,8 +532,8 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
         auto raw_cell = [&](int ip, int j, int kk) -> RawCell {
             const long long off = rowoff(ip, j) + kk;
             RawCell q;
-            q.a = wave_uniform(vin[CHK(off, g.npad)]);
-            if constexpr (MODE == kUpdateP) q.b = wave_uniform(vpold[CHK(off, g.npad)]);
+            q.a = wave_uniform(gin[CHK(off, g.npad)]);
+            if constexpr (MODE == kUpdateP) q.b = wave_uniform(gpold[CHK(off, g.npad)]);
             else q.b = 0;
             return q;
         };
@@ -482,11 +541,11 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
             if constexpr (MODE == kUpdateP) return vfma<V>(beta, q.b, q.a / diag_at<V>(rc, cdph, cihm, cihk));
             else return q.a;
         };
-        auto store2 = [&](V *dst, int ip, int j, V a0, V a1) {
+        auto store2 = [&](GPtr<V> dst, int ip, int j, V a0, V a1) {
             P2 o;
             o.x = v0 ? a0 : V(0);
             o.y = v1 ? a1 : V(0);
-            if (lane_on) *reinterpret_cast<P2 *>(dst + CHK(rowoff(ip, j) + kc, g.npad - 1)) = o;
+            if (lane_on) *(GPtr<P2>)(dst + CHK(rowoff(ip, j) + kc, g.npad - 1)) = o;
         };
 
         V q0[M][2], q1[M][2], q2[M][2];
@@ -498,14 +557,14 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 raw[m] = raw_row(ipc, min(j0 + m, nt - 1));
-                if constexpr (MODE == kUpdateP) rcs[m] = rows[CHK(ipc * nt + min(j0 + m, nt - 1), nr * nt)];
+                if constexpr (MODE == kUpdateP) rcs[m] = load_row(crows, CHK(ipc * nt + min(j0 + m, nt - 1), nr * nt));
             }
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int j = j0 + m;
                 eval_row(raw[m], rcs[m], ip_on && j < nt, dst[m][0], dst[m][1]);
                 if constexpr (MODE == kUpdateP) {
-                    if (store && j < nt) store2(vout, ip, j, dst[m][0], dst[m][1]);
+                    if (store && j < nt) store2(gout, ip, j, dst[m][0], dst[m][1]);
                 }
             }
         };
@@ -523,21 +582,21 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int jc = min(j0 + m, nt - 1);
-                rc[m] = rows[CHK(i * nt + jc, nr * nt)];
+                rc[m] = load_row(crows, CHK(i * nt + jc, nr * nt));
                 nxt[m] = raw_row(ipn, jc);
-                if constexpr (MODE == kUpdateP) rcn[m] = rows[CHK(ipn * nt + jc, nr * nt)];
+                if constexpr (MODE == kUpdateP) rcn[m] = load_row(crows, CHK(ipn * nt + jc, nr * nt));
                 cl[m] = raw_cell(i, jc, kl);
                 cr[m] = raw_cell(i, jc, kr);
                 if constexpr (MODE == kUpdateR) {
-                    rv[m] = ld2(vout, rowoff(i, jc) + kc);
-                    xv[m] = ld2(vout2, rowoff(i, jc) + kc);
+                    rv[m] = ld2(gout, rowoff(i, jc) + kc);
+                    xv[m] = ld2(gout2, rowoff(i, jc) + kc);
                 }
             }
             hraw[0] = raw_row(i, jlo);
             hraw[1] = raw_row(i, jhi);
             if constexpr (MODE == kUpdateP) {
-                rch[0] = rows[CHK(i * nt + jlo, nr * nt)];
-                rch[1] = rows[CHK(i * nt + jhi, nr * nt)];
+                rch[0] = load_row(crows, CHK(i * nt + jlo, nr * nt));
+                rch[1] = load_row(crows, CHK(i * nt + jhi, nr * nt));
             }
             // ---- next layer's operand (stored as the new direction in update-p) ----
 #pragma unroll
@@ -545,7 +604,7 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
                 const int j = j0 + m;
                 eval_row(nxt[m], rcn[m], i + 1 < nr && j < nt, q2[m][0], q2[m][1]);
                 if constexpr (MODE == kUpdateP) {
-                    if (i + 1 < i1 && j < nt) store2(vout, i + 1, j, q2[m][0], q2[m][1]);
+                    if (i + 1 < i1 && j < nt) store2(gout, i + 1, j, q2[m][0], q2[m][1]);
                 }
             }
             V hlo0, hlo1, hhi0, hhi1;
@@ -586,19 +645,19 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
                     ap[e] = ve[e] ? vfma<V>(dph[e], t, (V)r_.pq * u) : V(0);
                 }
                 if constexpr (MODE == kApply) {
-                    if (row_on) store2(vout, i, j, ap[0], ap[1]);
+                    if (row_on) store2(gout, i, j, ap[0], ap[1]);
                 } else if constexpr (MODE == kResidual) {
                     V res[2];
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
-                        const double bval = (i == 0 && ve[e] && row_on) ? v.bplane[CHK((long long)min(j, nt - 1) * g.pitch + (e ? kc1 : kc0), (long long)nt * g.pitch)] : 0.0;
+                        const double bval = (i == 0 && ve[e] && row_on) ? gbp[CHK((long long)min(j, nt - 1) * g.pitch + (e ? kc1 : kc0), (long long)nt * g.pitch)] : 0.0;
                         res[e] = ve[e] ? (V)(bval - (double)ap[e]) : V(0);
                         const V z = res[e] / diag_at<V>(r_, dph[e] + (V)(!ve[e]), ihm[e], ihk[e]);
                         acc0 += wrow * ((double)res[e] * (double)z);
                         acc1 += wrow * ((double)res[e] * (double)res[e]);
                         acc2 += bval * bval;
                     }
-                    if (v.store_r && row_on) store2(vout, i, j, res[0], res[1]);
+                    if (v.store_r && row_on) store2(gout, i, j, res[0], res[1]);
                 } else if constexpr (MODE == kUpdateP) {
                     acc0 += wrow * ((double)c0 * (double)ap[0] + (double)c1 * (double)ap[1]);
                 } else {  // kUpdateR
@@ -613,8 +672,8 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
                         acc1 += wrow * ((double)rn[e] * (double)rn[e]);
                     }
                     if (row_on) {
-                        store2(vout, i, j, rn[0], rn[1]);
-                        store2(vout2, i, j, xn[0], xn[1]);
+                        store2(gout, i, j, rn[0], rn[1]);
+                        store2(gout2, i, j, xn[0], xn[1]);
                     }
                 }
             }
@@ -649,11 +708,30 @@ stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, con
                 s1 += red[q][1];
                 s2 += red[q][2];
             }
-            v.partial[CHK(b, g.nblocks)] = s0;
-            v.partial[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
-            v.partial[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
+            gpart[CHK(b, g.nblocks)] = s0;
+            gpart[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
+            gpart[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
     }
+}
+
+template <int M, int MODE, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_wave(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ vin,
+             const V *__restrict__ vpold, V *__restrict__ vout, V *__restrict__ vout2)
+{
+    wave_body<M, MODE, V>(g, v, rows, vin, vpold, vout, vout2, blockIdx.x);
+}
+
+template <int M, int MODE, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_wave_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
+{
+    const int bid = blockIdx.x;
+    const int s = batch_slot(slots, nslots, bid);
+    if (s < 0) return;
+    const BatchSlot<V> sl = slots[s];
+    wave_body<M, MODE, V>(sl.g, sl.v, sl.g.rows, sl.v.in, sl.v.pold, sl.out, sl.v.x, bid - sl.offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -896,6 +974,19 @@ __global__ void fill_kernel(V *p, long long n, V val)
         p[q] = val;
 }
 
+// Between the padded layout (rows of `pitch`) and the packed one (rows of np):
+// pack = 1: dst[row * np + k] = src[row * pitch + k]; pack = 0: the reverse.
+__global__ void repack_kernel(const double *src, double *dst, long long nrows, int np, int pitch, int pack)
+{
+    const long long n = nrows * np;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const long long row = q / np;
+        const long long padded = row * pitch + (q - row * np);
+        if (pack) dst[q] = src[padded];
+        else dst[padded] = src[q];
+    }
+}
+
 // Eq. (3) pole values: per radial layer, sum_k dphi_k Phi(i, ring, k) / (2 pi)
 // on the rings j = 0 (north) and j = nt-1 (south).  One workgroup per layer.
 __global__ void __launch_bounds__(256)
@@ -1034,20 +1125,48 @@ template hipError_t launch_stencil<double>(int, int, const GridArgs &, const Ste
 template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t,
                                          hipEvent_t, hipEvent_t);
 
-template <typename V>
-hipError_t launch_stencil_batch(int mode, const BatchSlot<V> *slots, int nslots, int total_blocks, hipStream_t s)
+template <int TJ, typename V>
+hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)
 {
-    if (total_blocks <= 0) return hipSuccess;
-    const dim3 grid(total_blocks), block(kThreads);
+    const dim3 block(kThreads);
     switch (mode) {
-    case kUpdateP: stencil_march_batch<8, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
-    case kUpdateR: stencil_march_batch<8, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateP: stencil_march_batch<TJ, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateR: stencil_march_batch<TJ, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template hipError_t launch_stencil_batch<double>(int, const BatchSlot<double> *, int, int, hipStream_t);
-template hipError_t launch_stencil_batch<float>(int, const BatchSlot<float> *, int, int, hipStream_t);
+
+template <int M, typename V>
+hipError_t launch_wave_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)
+{
+    const dim3 block(kThreads);
+    switch (mode) {
+    case kUpdateP: stencil_wave_batch<M, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateR: stencil_wave_batch<M, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+hipError_t launch_stencil_batch(int mode, int tile, const BatchSlot<V> *slots, int nslots, int total_blocks,
+                                hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 grid(total_blocks);
+    switch (tile) {
+    case kTileMarch8: return launch_march_batch<8, V>(mode, slots, nslots, grid, s);
+    case kTileMarch16: return launch_march_batch<16, V>(mode, slots, nslots, grid, s);
+    case kTileMarch32: return launch_march_batch<32, V>(mode, slots, nslots, grid, s);
+    case kTileWave2: return launch_wave_batch<2, V>(mode, slots, nslots, grid, s);
+    case kTileWave4: return launch_wave_batch<4, V>(mode, slots, nslots, grid, s);
+    case kTileWave8: return launch_wave_batch<8, V>(mode, slots, nslots, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_stencil_batch<double>(int, int, const BatchSlot<double> *, int, int, hipStream_t);
+template hipError_t launch_stencil_batch<float>(int, int, const BatchSlot<float> *, int, int, hipStream_t);
 
 hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipStream_t s)
 {
@@ -1080,6 +1199,16 @@ hipError_t launch_fill(V *p, long long n, V val, hipStream_t s)
 }
 template hipError_t launch_fill<double>(double *, long long, double, hipStream_t);
 template hipError_t launch_fill<float>(float *, long long, float, hipStream_t);
+
+hipError_t launch_repack(const double *src, double *dst, long long nrows, int np, int pitch, bool pack, hipStream_t s)
+{
+    const long long n = nrows * np;
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    repack_kernel<<<(unsigned)blocks, 256, 0, s>>>(src, dst, nrows, np, pitch, pack ? 1 : 0);
+    return hipGetLastError();
+}
 
 unsigned take_oob_line(hipStream_t s)
 {

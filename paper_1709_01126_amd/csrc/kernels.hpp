@@ -41,9 +41,11 @@ bool checked_build();
 
 hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s);
 
-// Batched passes over a device slot table (tile kTileMarch8 in every slot).
+// Batched passes over a device slot table: every active slot runs the given
+// tile shape (the same for all slots of a launch).
 template <typename V>
-hipError_t launch_stencil_batch(int mode, const BatchSlot<V> *slots, int nslots, int total_blocks, hipStream_t s);
+hipError_t launch_stencil_batch(int mode, int tile, const BatchSlot<V> *slots, int nslots, int total_blocks,
+                                hipStream_t s);
 hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipStream_t s);
 
 hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, int nt, int np, int pitch,
@@ -51,6 +53,10 @@ hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, 
 
 template <typename V>
 hipError_t launch_fill(V *p, long long n, V val, hipStream_t s);
+
+// Padded <-> packed copy of nrows rows (pack: rows of pitch -> rows of np;
+// otherwise the reverse, leaving the padding of dst untouched).  Device memory.
+hipError_t launch_repack(const double *src, double *dst, long long nrows, int np, int pitch, bool pack, hipStream_t s);
 
 // Refinement helpers.
 // r32 = float(r64 * sc->scale); e32 = 0; p32 = 0 (all npad elements)

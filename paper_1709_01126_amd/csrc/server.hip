@@ -6,19 +6,29 @@
 //      In FP32-refined mode a finished inner solve instead gets its
 //      correction, an FP64 outer test, and either a new inner solve or
 //      retirement;
-//   2. admits queued requests while a slot is free and their device
-//      footprint fits the HBM budget.  Per-grid contexts (tables and vectors)
-//      are cached and reused; idle ones are evicted oldest first when the
-//      budget needs it;
-//   3. replays one captured graph of m batched PCG iterations.  Each kernel of
-//      it covers every active slot (a slot table in device memory maps
-//      workgroups to slots), and slots that have converged are masked by their
-//      own done flags.
-// The graph is captured once for a fixed slot capacity and reads the slot
-// tables at run time, so requests join and leave between replays without
-// recapture.  Every slot runs exactly the launch shape, tile order and
-// reduction order of a single solve on the same grid, so each result is
-// bitwise the one the request would get alone.
+//   2. admits queued requests, in arrival order, while a slot is free, their
+//      device footprint fits the HBM budget, and the bytes that all active
+//      solves stream per iteration stay within the cache budget (by default
+//      the 256 MB memory-side cache) -- or the server is idle.  Solves that
+//      run from the cache alone are thus not batched into ones that would
+//      stream from HBM, and bandwidth-bound solves, which batching cannot
+//      speed up, run alone.  Per-grid contexts (tables and vectors) are
+//      cached and reused; idle ones are evicted oldest first when the budget
+//      needs it;
+//   3. queues one replay of a captured graph of m batched PCG iterations.
+//      Each kernel of it covers every active slot (a slot table in device
+//      memory maps workgroups to slots), and slots that have converged are
+//      masked by their own done flags.
+// A step queues its replay before it reads the statuses of the previous one,
+// so the device always has the next replay queued while the host decides.  A
+// slot that finished in replay k runs through replay k+1 as a no-op, and
+// retirement and admission are ordered after it on the same stream.
+// The graphs read the slot tables at run time, so requests join and leave
+// between replays without recapture; one graph is captured per launch width
+// (a power of two of workgroups) the first time a batch needs it.  Every slot
+// runs exactly the launch shape, tile order and reduction order of a single
+// solve on the same grid, so each result is bitwise the one the request gets
+// from pot3d_solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,6 +66,15 @@ struct Slot {
     Request *req = nullptr;
     bool active = false;
     int total_inner = 0, outer = 0, launches = 0;
+    unsigned phase = 0;   // bumped whenever the slot's solve (re)starts on the device
+};
+
+// What a queued replay covered: per slot, the request and phase at launch.
+struct Replay {
+    bool pending = false;
+    std::vector<Request *> req;
+    std::vector<unsigned> phase;
+    hipEvent_t done = nullptr;
 };
 
 constexpr int kBlockAlign = 8;   // slot offsets keep the XCD of a workgroup unchanged
@@ -66,12 +85,14 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
 struct pot3d_server {
     int device = 0, precision = POT3D_FP64, max_slots = 0, graph_m = 16;
-    int per_slot_blocks = 0, capacity = 0;
+    int tile_p = kTileMarch8, tile_r = kTileMarch8;   // launch shapes of every slot
     size_t budget = 0, used = 0;
-    hipStream_t stream = nullptr;
+    size_t cache_budget = size_t(256) << 20;   // bytes streamed per iteration by the active set
+    hipStream_t stream = nullptr, capture_stream = nullptr;
     std::deque<Request *> queue;
     std::map<long long, std::unique_ptr<Request>> requests;
     long long next_id = 1, finished = 0, replays = 0;
+    unsigned next_phase = 0;
     std::vector<Slot> slots;
     std::vector<pot3d_ctx *> idle;   // cached contexts, oldest first
     // slot tables [parity][slot]: update-p and update-r, FP64 or FP32
@@ -81,8 +102,11 @@ struct pot3d_server {
     std::vector<BatchSlot<double>> h_p64[2], h_r64[2];
     std::vector<BatchSlot<float>> h_p32[2], h_r32[2];
     std::vector<BatchFin> h_finp, h_finr;
-    DevScalars *h_status = nullptr;   // pinned, one per slot
-    hipGraphExec_t graph = nullptr;
+    DevScalars *h_status = nullptr;   // pinned, [2][slot]: statuses after the two latest replays
+    Replay replay[2];
+    int last = -1;                    // replay buffer of the most recent launch
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;   // (workgroups per launch, graph), widening
+    int need_blocks = 0;   // workgroups the active slots occupy (max over the two passes)
     std::chrono::steady_clock::time_point t0;
     std::string err;
 
@@ -121,15 +145,16 @@ hipError_t dalloc(T **p, size_t count)
 }
 
 template <typename V>
-int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr)
+int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr, int width,
+                    hipGraphExec_t *out)
 {
-    hipStream_t s = sv->stream;
+    hipStream_t s = sv->capture_stream;
     SV_TRY(sv, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int it = 0; it < sv->graph_m && e == hipSuccess; ++it) {
-        e = launch_stencil_batch<V>(kUpdateP, dp[it & 1], sv->max_slots, sv->capacity, s);
+        e = launch_stencil_batch<V>(kUpdateP, sv->tile_p, dp[it & 1], sv->max_slots, width, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinSigma, sv->d_finp, sv->max_slots, s);
-        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, dr[it & 1], sv->max_slots, sv->capacity, s);
+        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, sv->tile_r, dr[it & 1], sv->max_slots, width, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinRho, sv->d_finr, sv->max_slots, s);
     }
     hipGraph_t graph = nullptr;
@@ -139,9 +164,33 @@ int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *con
         return sfail(sv, POT3D_EDEVICE, std::string("batched graph capture: ") +
                                             hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    hipError_t e3 = hipGraphInstantiate(&sv->graph, graph, nullptr, nullptr, 0);
+    hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e3 != hipSuccess) return sfail(sv, POT3D_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return POT3D_OK;
+}
+
+// The narrowest captured graph that covers `need` workgroups, capturing one
+// (a power of two of at least 1024) if none does.
+int graph_for(pot3d_server *sv, int need, hipGraphExec_t *out)
+{
+    for (const auto &w : sv->graphs)
+        if (w.first >= need) {
+            *out = w.second;
+            return POT3D_OK;
+        }
+    int width = 1024;
+    while (width < need) width *= 2;
+    hipGraphExec_t g = nullptr;
+    const int rc = sv->precision == POT3D_FP64 ? capture_batched<double>(sv, sv->d_p64, sv->d_r64, width, &g)
+                                               : capture_batched<float>(sv, sv->d_p32, sv->d_r32, width, &g);
+    if (rc != POT3D_OK) return rc;
+    sv->graphs.emplace_back(width, g);
+    std::sort(sv->graphs.begin(), sv->graphs.end(),
+              [](const std::pair<int, hipGraphExec_t> &a, const std::pair<int, hipGraphExec_t> &b) {
+                  return a.first < b.first;
+              });
+    *out = g;
     return POT3D_OK;
 }
 
@@ -202,6 +251,7 @@ void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<Ba
         offp += round_up(c->grid_p.nblocks, kBlockAlign);
         offr += round_up(c->grid_r.nblocks, kBlockAlign);
     }
+    sv->need_blocks = std::max(offp, offr);
 }
 
 int upload_tables(pot3d_server *sv)
@@ -230,6 +280,14 @@ int upload_tables(pot3d_server *sv)
     // the tables are pageable host vectors: finish the copies before they change
     SV_TRY(sv, hipStreamSynchronize(s));
     return POT3D_OK;
+}
+
+// Bytes one iteration of a request streams: FP64 x, r and two directions, or
+// in refined mode the four FP32 vectors of the inner solve.
+size_t stream_bytes(const pot3d_server *sv, const Request *r)
+{
+    const size_t pitch = (size_t)(r->np + 7) / 8 * 8;
+    return (size_t)r->nr * r->nt * pitch * (sv->precision == POT3D_FP32_REFINED ? 16 : 32);
 }
 
 bool same_grid(const pot3d_ctx *c, const Request *r)
@@ -272,9 +330,9 @@ int acquire_context(pot3d_server *sv, Request *r, pot3d_ctx **ctx)
     int rc = create_context(r->rf.data(), r->nr, r->tf.data(), r->nt, r->pf.data(), r->np, POT3D_UPPER_SOURCE_SURFACE,
                             sv->precision, sv->device, true, &c);
     if (rc != POT3D_OK) return sfail(sv, rc, pot3d_last_error(nullptr));
-    if (c->grid_p.nblocks > sv->per_slot_blocks || c->grid_r.nblocks > sv->per_slot_blocks) {
+    if (c->tile_p != sv->tile_p || c->tile_r != sv->tile_r) {
         free_ctx(c);
-        return sfail(sv, POT3D_EINVAL, "grid needs more workgroups per launch than a server slot holds");
+        return sfail(sv, POT3D_EINVAL, "context launch shape differs from the server's batched kernels");
     }
     sv->used += context_bytes(c);
     *ctx = c;
@@ -324,6 +382,7 @@ int refined_advance(pot3d_server *sv, Slot &sl)
         return retire(sv, sl, out, sl.total_inner, sl.outer);
     }
     SV_CALL(sv, c, refined_start_inner(c, sv->stream, r->tol, r->maxit - sl.total_inner, out.relres));
+    sl.phase = ++sv->next_phase;
     return POT3D_OK;
 }
 
@@ -334,6 +393,7 @@ int admit(pot3d_server *sv, Slot &sl, Request *r, pot3d_ctx *c)
     sl.ctx = c;
     sl.req = r;
     sl.active = true;
+    sl.phase = ++sv->next_phase;
     r->t_admit = sv->now();
     SV_TRY(sv, hipEventRecord(c->ev_t0, s));
     SV_TRY(sv, hipMemcpyAsync(c->br, r->br.data(), r->br.size() * sizeof(double), hipMemcpyHostToDevice, s));
@@ -379,15 +439,7 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return sfail(nullptr, POT3D_EDEVICE, "hipMemGetInfo failed");
     sv->budget = hbm_budget_bytes > 0.0 ? (size_t)hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
-    // a slot holds up to half of the resident workgroups of the batched kernels
-    hipDeviceProp_t prop{};
-    const int ncu = (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-                        ? prop.multiProcessorCount
-                        : 256;
-    const int per_cu = precision == POT3D_FP64 ? stencil_blocks_per_cu<double>(kUpdateP, kTileMarch8)
-                                               : stencil_blocks_per_cu<float>(kUpdateP, kTileMarch8);
-    sv->per_slot_blocks = round_up(std::max(1024, std::max(1, per_cu) * ncu), kBlockAlign);
-    sv->capacity = sv->per_slot_blocks * max_slots;
+    default_tiles(precision, &sv->tile_p, &sv->tile_r);
     sv->slots.assign(max_slots, Slot{});
     for (int par = 0; par < 2; ++par) {
         sv->h_p64[par].assign(max_slots, BatchSlot<double>{});
@@ -403,6 +455,12 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
         return code;
     };
     hipError_t e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        p->replay[b].req.assign(max_slots, nullptr);
+        p->replay[b].phase.assign(max_slots, 0);
+        e = hipEventCreateWithFlags(&p->replay[b].done, hipEventDisableTiming);
+    }
     for (int par = 0; par < 2 && e == hipSuccess; ++par) {
         if (precision == POT3D_FP64) {
             e = dalloc(&p->d_p64[par], max_slots);
@@ -414,7 +472,7 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
     }
     if (e == hipSuccess) e = dalloc(&p->d_finp, max_slots);
     if (e == hipSuccess) e = dalloc(&p->d_finr, max_slots);
-    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_status), max_slots * sizeof(DevScalars),
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&p->h_status), 2 * max_slots * sizeof(DevScalars),
                                            hipHostMallocDefault);
     if (e != hipSuccess) {
         sfail(nullptr, POT3D_EDEVICE, std::string("server allocation: ") + hipGetErrorString(e));
@@ -424,8 +482,9 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
         g_server_error = p->err;
         return bail(POT3D_EDEVICE);
     }
-    const int rc = precision == POT3D_FP64 ? capture_batched<double>(p, p->d_p64, p->d_r64)
-                                           : capture_batched<float>(p, p->d_p32, p->d_r32);
+    // the graph for the narrowest width, so that capture problems show here
+    hipGraphExec_t g0 = nullptr;
+    const int rc = graph_for(p, 1, &g0);
     if (rc != POT3D_OK) {
         g_server_error = p->err;
         return bail(rc);
@@ -468,18 +527,52 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
     DeviceGuard guard(sv->device);
     if (!guard.ok) return sfail(sv, POT3D_EDEVICE, "hipSetDevice failed");
     hipStream_t s = sv->stream;
+    const int prev = sv->last;
+    // 1. queue the next replay of the active slots (the tables are current),
+    //    with a copy of each slot's scalars after it
+    int launched = -1;
+    int active = 0;
+    for (const Slot &sl : sv->slots) active += sl.active ? 1 : 0;
+    if (active > 0) {
+        const int b = prev == 0 ? 1 : 0;
+        hipGraphExec_t g = nullptr;
+        const int rc = graph_for(sv, sv->need_blocks, &g);
+        if (rc != POT3D_OK) return rc;
+        SV_TRY(sv, hipGraphLaunch(g, s));
+        ++sv->replays;
+        Replay &rp = sv->replay[b];
+        for (int q = 0; q < sv->max_slots; ++q) {
+            Slot &sl = sv->slots[q];
+            rp.req[q] = sl.active ? sl.req : nullptr;
+            rp.phase[q] = sl.phase;
+            if (!sl.active) continue;
+            sl.launches += 1;
+            DevScalars *src = sv->precision == POT3D_FP64 ? sl.ctx->sc : sl.ctx->sc32;
+            SV_TRY(sv, hipMemcpyAsync(&sv->h_status[b * sv->max_slots + q], src, sizeof(DevScalars),
+                                      hipMemcpyDeviceToHost, s));
+        }
+        SV_TRY(sv, hipEventRecord(rp.done, s));
+        rp.pending = true;
+        launched = b;
+    }
+    // 2. slots whose current solve ended in the previous replay (the one just
+    //    queued is a no-op for them; what follows is ordered after it)
     bool changed = false;
-    // 1. slots whose current solve ended in the last replay
-    for (Slot &sl : sv->slots) {
-        if (!sl.active) continue;
-        const int q = (int)(&sl - sv->slots.data());
-        const DevScalars st = sv->h_status[q];
-        if (!st.done) continue;
-        changed = true;
-        if (sv->precision == POT3D_FP64) {
-            const int rc = retire(sv, sl, st, st.k, 1);
-            if (rc != POT3D_OK) return rc;
-        } else {
+    if (prev >= 0 && sv->replay[prev].pending) {
+        Replay &rp = sv->replay[prev];
+        SV_TRY(sv, hipEventSynchronize(rp.done));
+        rp.pending = false;
+        for (int q = 0; q < sv->max_slots; ++q) {
+            Slot &sl = sv->slots[q];
+            if (!sl.active || rp.req[q] != sl.req || rp.phase[q] != sl.phase) continue;
+            const DevScalars st = sv->h_status[prev * sv->max_slots + q];
+            if (!st.done) continue;
+            changed = true;
+            if (sv->precision == POT3D_FP64) {
+                const int rc = retire(sv, sl, st, st.k, 1);
+                if (rc != POT3D_OK) return rc;
+                continue;
+            }
             sl.total_inner += st.k;
             sl.outer += 1;
             if (st.status == POT3D_EBREAKDOWN) {
@@ -494,10 +587,20 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
             if (rc != POT3D_OK) return rc;
         }
     }
-    // 2. admissions
+    sv->last = launched;
+    // 3. admissions
+    size_t streaming = 0;
+    int running = 0;
+    for (const Slot &sl : sv->slots)
+        if (sl.active) {
+            streaming += stream_bytes(sv, sl.req);
+            ++running;
+        }
     for (Slot &sl : sv->slots) {
         if (sl.active || sv->queue.empty()) continue;
         Request *r = sv->queue.front();
+        const size_t sb = stream_bytes(sv, r);
+        if (running > 0 && sv->cache_budget > 0 && streaming + sb > sv->cache_budget) break;
         pot3d_ctx *c = nullptr;
         int rc = acquire_context(sv, r, &c);
         if (rc != POT3D_OK) {   // the request cannot run on this server
@@ -513,26 +616,17 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
         changed = true;
         rc = admit(sv, sl, r, c);
         if (rc != POT3D_OK) return rc;
+        if (sl.active) {
+            streaming += sb;
+            ++running;
+        }
     }
-    // 3. one replay of the batched iterations
-    int active = 0;
-    for (const Slot &sl : sv->slots) active += sl.active ? 1 : 0;
     if (changed) {
         const int rc = upload_tables(sv);
         if (rc != POT3D_OK) return rc;
     }
-    if (active > 0) {
-        SV_TRY(sv, hipGraphLaunch(sv->graph, s));
-        ++sv->replays;
-        for (Slot &sl : sv->slots) {
-            if (!sl.active) continue;
-            const int q = (int)(&sl - sv->slots.data());
-            sl.launches += 1;
-            DevScalars *src = sv->precision == POT3D_FP64 ? sl.ctx->sc : sl.ctx->sc32;
-            SV_TRY(sv, hipMemcpyAsync(&sv->h_status[q], src, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        }
-        SV_TRY(sv, hipStreamSynchronize(s));
-    }
+    active = 0;
+    for (const Slot &sl : sv->slots) active += sl.active ? 1 : 0;
     if (n_active) *n_active = active;
     if (n_queued) *n_queued = (int)sv->queue.size();
     if (n_finished) *n_finished = sv->finished;
@@ -566,6 +660,14 @@ int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_reque
     return POT3D_OK;
 }
 
+int pot3d_server_set_cache_budget(pot3d_server *sv, double bytes)
+{
+    if (!sv) return sfail(nullptr, POT3D_EINVAL, "server is NULL");
+    if (!(bytes >= 0.0) || !std::isfinite(bytes)) return sfail(sv, POT3D_EINVAL, "bytes must be finite and >= 0");
+    sv->cache_budget = (size_t)bytes;
+    return POT3D_OK;
+}
+
 int pot3d_server_get_stats(const pot3d_server *sv, pot3d_server_stats *out)
 {
     if (!sv || !out) return sfail(const_cast<pot3d_server *>(sv), POT3D_EINVAL, "server and out are required");
@@ -591,12 +693,16 @@ void pot3d_server_destroy(pot3d_server *sv)
     for (Slot &sl : sv->slots)
         if (sl.ctx) free_ctx(sl.ctx);
     for (pot3d_ctx *c : sv->idle) free_ctx(c);
-    if (sv->graph) (void)hipGraphExecDestroy(sv->graph);
+    for (auto &g : sv->graphs)
+        if (g.second) (void)hipGraphExecDestroy(g.second);
     void *bufs[] = {sv->d_p64[0], sv->d_p64[1], sv->d_r64[0], sv->d_r64[1], sv->d_p32[0], sv->d_p32[1],
                     sv->d_r32[0], sv->d_r32[1], sv->d_finp, sv->d_finr};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (sv->h_status) (void)hipHostFree(sv->h_status);
+    for (Replay &r : sv->replay)
+        if (r.done) (void)hipEventDestroy(r.done);
+    if (sv->capture_stream) (void)hipStreamDestroy(sv->capture_stream);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
     delete sv;
 }

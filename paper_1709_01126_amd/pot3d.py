@@ -26,7 +26,8 @@ EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_de
             "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement", "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
-            "pot3d_server_get_stats", "pot3d_server_destroy", "pot3d_server_last_error")
+            "pot3d_server_set_cache_budget", "pot3d_server_get_stats", "pot3d_server_destroy",
+            "pot3d_server_last_error")
 
 
 class pot3d_stats(ctypes.Structure):
@@ -108,6 +109,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_server_step.restype = i
     lib.pot3d_server_result.argtypes = [vp, ll, d, ctypes.POINTER(pot3d_request_info)]
     lib.pot3d_server_result.restype = i
+    lib.pot3d_server_set_cache_budget.argtypes = [vp, ctypes.c_double]
+    lib.pot3d_server_set_cache_budget.restype = i
     lib.pot3d_server_get_stats.argtypes = [vp, ctypes.POINTER(pot3d_server_stats)]
     lib.pot3d_server_get_stats.restype = i
     lib.pot3d_server_destroy.argtypes = [vp]
@@ -333,6 +336,10 @@ def pot3d_server_result(sv, rid, phi_out=None):
     return st, info.as_dict()
 
 
+def pot3d_server_set_cache_budget(sv, nbytes):
+    return load().pot3d_server_set_cache_budget(sv, float(nbytes))
+
+
 def pot3d_server_get_stats(sv):
     s = pot3d_server_stats()
     st = load().pot3d_server_get_stats(sv, ctypes.byref(s))
@@ -384,6 +391,9 @@ class Server:
             raise Pot3dError(EINVAL, f"request {rid} is not done")
         del self.shapes[rid]
         return phi, info
+
+    def set_cache_budget(self, nbytes):
+        self._check(pot3d_server_set_cache_budget(self.sv, nbytes))
 
     def stats(self):
         st, s = pot3d_server_get_stats(self.sv)

@@ -126,4 +126,5 @@ def test_server_rejects_invalid_arguments():
     assert P.pot3d_server_step(None)[0] == P.EINVAL
     assert P.pot3d_server_result(None, 1)[0] == P.EINVAL
     assert P.pot3d_server_get_stats(None)[0] == P.EINVAL
+    assert P.pot3d_server_set_cache_budget(None, 1e9) == P.EINVAL
     P.pot3d_server_destroy(None)

@@ -141,3 +141,25 @@ def test_server_edge_cases():
         for key, (b, tol, maxit) in {"cap": (br, 1e-10, 5), "fixed": (br, 0.0, 37)}.items():
             phi_a, st_a, it_a, _ = s.solve(b, tol, maxit)
             assert np.array_equal(res[key][0], phi_a) and res[key][1]["iters"] == it_a
+
+
+def test_server_cache_budget():
+    # 1 byte: no two solves share a replay; 0: no limit.  Results unchanged.
+    reqs = requests([GRIDS[4], GRIDS[5], GRIDS[3], GRIDS[4]])
+    ref = alone(reqs, P.FP64)
+    for budget, want_peak in ((1.0, 1), (0.0, 4)):
+        with P.Server(precision=P.FP64, max_slots=4) as sv:
+            sv.set_cache_budget(budget)
+            ids = [sv.submit(rf, tf, pf, br, tol, maxit) for _, rf, tf, pf, br, tol, maxit in reqs]
+            peak = 0
+            for _ in range(100_000):
+                active, _, finished = sv.step()
+                peak = max(peak, active)
+                if finished == len(ids):
+                    break
+            out = [sv.take(rid) for rid in ids]
+            with pytest.raises(P.Pot3dError):
+                sv.set_cache_budget(-1.0)
+        assert peak == want_peak, (budget, peak)
+        for (phi_a, st_a, it_a, _), (phi_s, info) in zip(ref, out):
+            assert info["status"] == st_a and info["iters"] == it_a and np.array_equal(phi_s, phi_a)
