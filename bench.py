@@ -120,12 +120,18 @@ def cpu_baseline(w, faces, br, budget_s: float):
     rf, tf, pf = faces
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
-    # a warm-up run, a short run to size the sample, then a run of about budget_s seconds
+    # a warm-up run, two short runs to size the sample (per-iteration time and
+    # the per-call setup), then a run of about budget_s seconds
     oracle.pcg(coef, b, 0.0, 1)
     t0 = time.perf_counter()
-    oracle.pcg(coef, b, 0.0, 5)
-    per = max(1e-3, (time.perf_counter() - t0) / 5)
-    k = max(3, int(budget_s / per))
+    oracle.pcg(coef, b, 0.0, 4)
+    t4 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.pcg(coef, b, 0.0, 20)
+    t20 = time.perf_counter() - t0
+    per = max(1e-4, (t20 - t4) / 16)
+    setup = max(0.0, t4 - 4 * per)
+    k = max(3, int((budget_s - setup) / per))
     t0 = time.perf_counter()
     _, iters, _, _ = oracle.pcg(coef, b, 0.0, k)
     dt = time.perf_counter() - t0
@@ -280,7 +286,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="bipole_151x301x601")
-    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),

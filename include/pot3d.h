@@ -155,13 +155,14 @@ int pot3d_pole_values(const pot3d_ctx *ctx, double *north, double *south);
 int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
 
 /*
- * Benchmark helper: launch the two per-iteration stencil kernels (the p
- * update with A p and p.Ap, then the r/x update with r.z and r.r) alternately,
- * `reps` times each, on the context's stream as in the iteration, and report
- * each kernel's average duration in ms from hipEvents recorded between the
- * launches.  FP32-refined contexts time the FP32
- * inner kernels.  It runs on the vectors the context holds and overwrites
- * them; a later solve re-initializes everything.
+ * Benchmark helper: average duration in ms of the two per-iteration stencil
+ * kernels (the p update with A p and p.Ap; the r/x update with r.z and r.r)
+ * as they run in a solve: a graph of `reps` iterations in the solve's order
+ * is replayed twice back to back on the context's stream, and in the second
+ * replay each stencil launch records its first workgroup's start and its
+ * last workgroup's end on the device wall clock.  FP32-refined
+ * contexts time the FP32 inner kernels.  It runs on the vectors the context
+ * holds and overwrites them; a later solve re-initializes everything.
  */
 int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
 

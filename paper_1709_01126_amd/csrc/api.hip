@@ -28,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "context.hpp"
@@ -184,10 +185,10 @@ int resident_blocks(const pot3d_ctx *c, int mode, int tile)
 }
 
 // Default shapes (measured on MI355X at 151 x 301 x 601).  FP64: both
-// iteration passes on the 8-row LDS-plane kernel, with radial chunks sized so
-// one launch fills at most half of the resident workgroup slots: fewer, longer
-// chunks repeat fewer boundary layers, and a single wave of workgroups leaves
-// no tail.  FP32 passes move half the bytes per cell, so a workgroup keeps
+// iteration passes on the 8-row LDS-plane kernel, with radial chunks sized for
+// about 3 workgroups per CU: fewer, longer chunks repeat fewer boundary
+// layers, and a launch that fits the resident slots runs as one wave of
+// workgroups with no tail.  FP32 passes move half the bytes per cell, so a workgroup keeps
 // fewer bytes in flight and more of them are needed: the p update runs
 // 16-row tiles at about 6 workgroups per CU, and the r/x update runs on the
 // two-row wavefront kernel with about 4096 workgroups.
@@ -212,8 +213,7 @@ void choose_launch(pot3d_ctx *c)
     const int tp = env_int("POT3D_TARGET_BLOCKS_P", tb), tr = env_int("POT3D_TARGET_BLOCKS_R", tb);
     auto dflt_target = [&](int mode, int tile) {
         if (tile_is_wave(tile)) return 4096;
-        if (fp32) return 6 * c->num_cu;
-        return resident_blocks(c, mode, tile) / 2;
+        return std::min(resident_blocks(c, mode, tile), (fp32 ? 6 : 3) * c->num_cu);
     };
     c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : dflt_target(kUpdateP, c->tile_p));
     c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : dflt_target(kUpdateR, c->tile_r));
@@ -569,66 +569,108 @@ int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStrea
     return fin.status;
 }
 
-// Average duration of the two iteration kernels, launched alternately
-// (update-p, update-r) `reps` times on the context stream as in the iteration.
-// Each launch carries start/stop events stamped by the dispatch itself.  Runs
-// on the vectors the context holds.
+// Average duration of the two iteration kernels as they run in a solve: a
+// graph of `reps` iterations in the solve's order (p update, alpha, r/x
+// update, beta), replayed twice back to back (warm-up, then timed).  In this
+// graph each stencil launch records, on the device wall clock, its first
+// workgroup's start and its last workgroup's end; host events around the
+// timed replay set the clock's scale.  (Host events on single launches are no
+// substitute: a launch that signals an event to the host runs longer, and the
+// r/x update starts on the tiles the p update touched last, whose lines are
+// then still in the memory-side cache, so it is timed in that sequence.)  The
+// stencil kernels ignore the done flag.  FP64: a fixed-count PCG from x = 0
+// on the context's right-hand side; FP32: fixed scalars.  Runs on (and
+// overwrites) the context's vectors.
 template <typename V>
 int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_p, double *ms_r)
 {
     hipStream_t s = ctx->stream;
-    DevScalars st{};
-    st.alpha = 1e-3;
-    st.beta = 0.5;
-    st.rho = 1.0;
-    st.bnorm = 1.0;
-    st.tol = 0.0;
-    st.maxit = 1 << 30;
-    ctx->h_sc[0] = st;
-    HIP_TRY(ctx, hipMemcpyAsync(sc, &ctx->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
-    StencilVecs<V> a{};
-    a.sc = sc;
-    a.partial = ctx->partial;
-    a.in = r;
-    a.pold = p0;
-    a.pnew = p1;
-    a.ignore_done = 1;
-    StencilVecs<V> bv{};
-    bv.sc = sc;
-    bv.partial = ctx->partial;
-    bv.in = p1;
-    bv.r = r;
-    bv.x = x;
-    bv.ignore_done = 1;
-    std::vector<hipEvent_t> ev(4 * (size_t)reps, nullptr);
-    for (auto &e : ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            for (auto &f : ev)
-                if (f) (void)hipEventDestroy(f);
-            return fail(ctx, POT3D_EDEVICE, "hipEventCreate failed");
-        }
+    const int m = std::max(1, reps);
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
+        return fail(ctx, POT3D_EDEVICE, "device wall-clock rate unavailable");
+    if constexpr (std::is_same<V, double>::value) {
+        // a real fixed-count PCG from x = 0 on the context's right-hand side
+        HIP_TRY(ctx, launch_fill<double>(ctx->x, ctx->npad, 0.0, s));
+        const int rc = start_fp64(ctx, s, 0.0, 1 << 30);
+        if (rc != POT3D_OK) return rc;
+    } else {
+        DevScalars st{};
+        st.alpha = 1e-3;
+        st.beta = 0.5;
+        st.rho = 1.0;
+        st.bnorm = 1.0;
+        st.tol = 0.0;
+        st.maxit = 1 << 30;
+        ctx->h_sc[0] = st;
+        HIP_TRY(ctx, hipMemcpyAsync(sc, &ctx->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
     }
-    int rc = POT3D_OK;
-    hipError_t e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s);   // warm-up
-    if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s);
-    for (int q = 0; q < reps && e == hipSuccess; ++q) {
-        e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s, ev[4 * q], ev[4 * q + 1]);
-        if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s, ev[4 * q + 2], ev[4 * q + 3]);
+    // per iteration: p update start, end; r/x update start, end
+    std::vector<unsigned long long> init(4 * (size_t)m), stamps(4 * (size_t)m);
+    for (int q = 0; q < 2 * m; ++q) {
+        init[2 * q] = ~0ull;
+        init[2 * q + 1] = 0ull;
     }
+    unsigned long long *d_ts = nullptr;
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&d_ts), init.size() * sizeof(unsigned long long)));
+    V *pb[2] = {p0, p1};
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int it = 0; it < m && e == hipSuccess; ++it) {
+        StencilVecs<V> a{};
+        a.sc = sc;
+        a.partial = ctx->partial;
+        a.in = r;
+        a.pold = pb[it & 1];
+        a.pnew = pb[(it + 1) & 1];
+        a.ignore_done = 1;
+        a.tstamp = d_ts + 4 * it;
+        StencilVecs<V> bv{};
+        bv.sc = sc;
+        bv.partial = ctx->partial;
+        bv.in = pb[(it + 1) & 1];
+        bv.r = r;
+        bv.x = x;
+        bv.ignore_done = 1;
+        bv.tstamp = d_ts + 4 * it + 2;
+        e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s);
+        if (e == hipSuccess) e = launch_finish(kFinSigma, sc, ctx->partial, ctx->grid_p.nblocks, s);
+        if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s);
+        if (e == hipSuccess) e = launch_finish(kFinRho, sc, ctx->partial, ctx->grid_r.nblocks, s);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    double tp = 0.0, tr = 0.0;
+    const int timed = m;
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);   // warm-up
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ts, init.data(), init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_t0, s);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_t1, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stamps.data(), d_ts, stamps.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    double sp = 0.0, sr = 0.0;
-    for (int q = 0; q < reps && e == hipSuccess; ++q) {
-        float t1 = 0.f, t2 = 0.f;
-        e = hipEventElapsedTime(&t1, ev[4 * q], ev[4 * q + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&t2, ev[4 * q + 2], ev[4 * q + 3]);
-        sp += t1;
-        sr += t2;
+    // device ticks -> ms: the replay's span on the device clock (first p
+    // update start to last r/x update end) against the same replay between
+    // host events
+    float span_ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&span_ms, ctx->ev_t0, ctx->ev_t1);
+    const double span_ticks = (double)(stamps[4 * (size_t)(m - 1) + 3] - stamps[0]);
+    const double ms_per_tick = (span_ticks > 0.0 && span_ms > 0.f) ? span_ms / span_ticks : 1.0 / khz;
+    for (int it = 0; it < m && e == hipSuccess; ++it) {
+        tp += (double)(stamps[4 * it + 1] - stamps[4 * it]) * ms_per_tick;
+        tr += (double)(stamps[4 * it + 3] - stamps[4 * it + 2]) * ms_per_tick;
     }
-    for (auto &f : ev) (void)hipEventDestroy(f);
-    if (e != hipSuccess) rc = fail(ctx, POT3D_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
-    *ms_p = sp / reps;
-    *ms_r = sr / reps;
-    return rc;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipFree(d_ts);
+    if (e != hipSuccess) return fail(ctx, POT3D_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
+    *ms_p = tp / timed;
+    *ms_r = tr / timed;
+    return POT3D_OK;
 }
 
 int create_context(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,

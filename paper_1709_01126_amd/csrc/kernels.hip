@@ -111,6 +111,7 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
     const CPtr<const DevScalars> csc = to_const(v.sc);
     const CPtr<const RowCoef> crows = to_const(rows);
     if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
+    if (v.tstamp && threadIdx.x == 0) atomicMin(&v.tstamp[0], wall_clock64());
 
     // Element accesses go through global-address-space pointers.  A batched
     // launch reads its pointers from the slot table, and the compiler would
@@ -344,6 +345,10 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
             gpart[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
     }
+    if (v.tstamp) {   // timing runs: this workgroup's end
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(&v.tstamp[1], wall_clock64());
+    }
 }
 
 template <int TJ, int MODE, typename V>
@@ -451,6 +456,7 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
     const CPtr<const DevScalars> csc = to_const(v.sc);
     const CPtr<const RowCoef> crows = to_const(rows);
     if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
+    if (v.tstamp && threadIdx.x == 0) atomicMin(&v.tstamp[0], wall_clock64());
     const GPtr<const V> gin = to_global(vin), gpold = to_global(vpold);
     const GPtr<V> gout = to_global(vout), gout2 = to_global(vout2);
     const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih), gbp = to_global(v.bplane);
@@ -712,6 +718,10 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
             gpart[CHK(g.nblocks + b, 3LL * g.nblocks)] = s1;
             gpart[CHK(2 * g.nblocks + b, 3LL * g.nblocks)] = s2;
         }
+    }
+    if (v.tstamp) {   // timing runs: this workgroup's end
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(&v.tstamp[1], wall_clock64());
     }
 }
 
@@ -1174,9 +1184,12 @@ hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s)
+hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s, hipEvent_t e0)
 {
-    finish_kernel<<<1, kFinThreads, 0, s>>>(which, sc, partial, nb);
+    if (e0)
+        hipExtLaunchKernelGGL(finish_kernel, dim3(1), dim3(kFinThreads), 0, s, e0, nullptr, 0, which, sc, partial, nb);
+    else
+        finish_kernel<<<1, kFinThreads, 0, s>>>(which, sc, partial, nb);
     return hipGetLastError();
 }
 

@@ -39,7 +39,9 @@ int stencil_blocks_per_cu(int mode, int tile);
 unsigned take_oob_line(hipStream_t s);
 bool checked_build();
 
-hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s);
+// e0 (optional): an event stamped with the dispatch's start.
+hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int nb, hipStream_t s,
+                         hipEvent_t e0 = nullptr);
 
 // Batched passes over a device slot table: every active slot runs the given
 // tile shape (the same for all slots of a launch).

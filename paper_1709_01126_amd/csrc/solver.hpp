@@ -82,6 +82,8 @@ struct StencilVecs {
     double *partial;  // [3][nblocks] per-workgroup partial sums
     int store_r;      // residual: 1 to store r, 0 to reduce only
     int ignore_done;  // 1: run even when sc->done is set
+    unsigned long long *tstamp;   // timing runs only: [0] earliest workgroup start, [1] latest
+                                  // workgroup end (device wall clock); NULL otherwise
 };
 
 // One slot of a batched stencil launch (device-resident table).  `out` is the
