@@ -200,7 +200,9 @@ const char *pot3d_version(void);
  * cached and reused by later requests on the same grid.  A solve that has
  * converged stops iterating at once, while the others go on.  Every result
  * is bitwise the one pot3d_solve gives for the same request on a context of
- * the same precision with the default launch shape.
+ * the same precision with the default launch shape, for grids whose vectors
+ * are below 512 MiB (above that, pot3d_solve switches to a shape for
+ * HBM-streaming grids, which the server does not use).
  * ------------------------------------------------------------------------ */
 typedef struct pot3d_server pot3d_server;
 

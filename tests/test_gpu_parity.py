@@ -320,3 +320,37 @@ def test_full_size_bipole_151x301x601():
     tr = oracle.true_relres(coef, b, phi)
     assert abs(tr - rr) <= 1e-2 * tr + 1e-13
     assert abs(tr - g["true_relres"]) <= 0.5 * g["true_relres"] + 1e-11
+
+
+def test_full_size_bipole_301x641x1281():
+    """One GPU's share at 301 x 641 x 1281 (247M unknowns, 2 GB per vector).
+    The oracle's fixed-count iterates (K = 5, 20) at sampled indices, written
+    by tests/golden/make_oracle_samples.py --fixed-only, must match to 1e-12
+    as at 151 x 301 x 601.  A full solve is too long for the oracle here, so
+    the converged GPU solution is checked by a property that holds at any
+    size: its true residual, recomputed with the oracle's own operator, meets
+    the workload's tolerance and matches the residual the library reports."""
+    g = _golden("bipole_301x641x1281")
+    w = WORKLOADS[g["workload"]]
+    rf, tf, pf = w.faces()
+    br = w.br((rf, tf, pf))
+    idx = np.array(g["indices"])
+    print(f"[full size] {w.describe()}", flush=True)
+    with P.Solver(rf, tf, pf) as s:
+        for K, ref in g["fixed"].items():
+            phik, st, it, _ = gpu_solve(s, br, 0.0, int(K))
+            assert st == P.ENOCONV and it == int(K)
+            err = np.abs(phik.ravel()[idx] - np.array(ref["phi"])).max() / ref["phi_max_abs"]
+            print(f"[full size] fixed K={K}: max rel diff {err:.2e}", flush=True)
+            assert err <= 1e-12, (K, err)
+        del phik
+        phi, st, it, rr = gpu_solve(s, br, w.tol, 500_000)
+        stats = s.stats()
+    print(f"[full size] gpu iters {it} true_relres {rr:.3e} solve {stats['solve_ms'] / 1e3:.1f} s", flush=True)
+    assert st == P.OK and rr <= w.tol * 1.01
+    coef = oracle.assemble(rf, tf, pf)
+    b = oracle.rhs(rf, tf, pf, br)
+    tr = oracle.true_relres(coef, b, phi)
+    print(f"[full size] oracle true_relres {tr:.3e}", flush=True)
+    assert tr <= w.tol * 1.01
+    assert abs(tr - rr) <= 1e-2 * tr + 1e-13
