@@ -62,6 +62,12 @@ enum pot3d_upper_bc {
                                          POT3D_EINVAL                                            */
 };
 
+enum pot3d_refine_mode {
+    POT3D_REFINE_RESTART = 0,   /* each inner FP32 solve starts a fresh PCG (p = 0)             */
+    POT3D_REFINE_RELIABLE = 1   /* each inner solve continues the previous one's search
+                                   direction after the FP64 residual replacement (default)     */
+};
+
 enum pot3d_precision {
     POT3D_FP64 = 0,          /* FP64 vectors, stencil and reductions throughout              */
     POT3D_FP32_REFINED = 1   /* FP32 inner PCG inside FP64 defect correction (see
@@ -125,8 +131,10 @@ int pot3d_solve(pot3d_ctx *ctx, const double *br, double tol, int maxit,
  * All work is ordered on `stream`; the call returns after the solve has
  * finished (it waits on the stream for the convergence flag).
  * In POT3D_FP32_REFINED contexts the outer loop recomputes r = b - A Phi in
- * FP64, solves A e = r with FP32 PCG to inner_tol (1e-4), and adds e to Phi in
- * FP64.  It repeats until the FP64 true residual is <= tol.
+ * FP64, runs FP32 PCG iterations on A e = r / ||r|| until their residual has
+ * dropped by inner_tol, and adds ||r|| e to Phi in FP64 (see
+ * pot3d_set_refinement_mode).  It repeats until the FP64 true residual is
+ * <= tol.
  */
 int pot3d_solve_device(pot3d_ctx *ctx, const double *d_br, const double *d_phi0, double *d_phi,
                        void *stream, double tol, int maxit, int *iters, double *relres_true);
@@ -168,10 +176,28 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
 
 /*
  * FP32-refined contexts only: tolerance of each inner FP32 solve, relative to
- * its right-hand side ||r||, in (0, 1) (default 1e-4), and the most outer
- * defect-correction cycles (default 50).  POT3D_EINVAL otherwise.
+ * its right-hand side ||r||, in (0, 1), and the most outer defect-correction
+ * cycles (default 50).  Default tolerance: 0.1 in reliable-update mode, 1e-4
+ * in restart mode (a reliable update every 1e-3 lets the FP32 recursion drift
+ * and can take many times the iterations).  POT3D_EINVAL otherwise.
  */
 int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer);
+
+/*
+ * FP32-refined contexts only: how an inner FP32 solve starts after the FP64
+ * residual r = b - A Phi has been recomputed and Phi corrected.
+ *   POT3D_REFINE_RESTART   a fresh PCG on r / ||r|| (plain defect correction);
+ *   POT3D_REFINE_RELIABLE  r / ||r|| replaces the FP32 recursive residual, and
+ *                          the last search direction (rescaled) and the beta
+ *                          recurrence continue: residual replacement as in the
+ *                          reliable-update CG of Sleijpen and van der Vorst.
+ *                          A continued segment is capped at twice the
+ *                          iterations of the one before (plus 64); after a
+ *                          segment that did not converge the next one
+ *                          restarts.  Default.
+ * POT3D_EINVAL for other contexts or modes.
+ */
+int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
 
 /* Free the context and all of its device memory.  NULL is a no-op. */
 void pot3d_destroy(pot3d_ctx *ctx);

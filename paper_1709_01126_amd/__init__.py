@@ -7,4 +7,4 @@ kernels are in ``csrc/`` and its interface is in ``include/pot3d.h``.
 buffers and streams.
 """
 from .pot3d import (EBREAKDOWN, EDEVICE, EINVAL, ENOCONV, ENOMEM, FP32_REFINED, FP64, OK,  # noqa: F401
-                    UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Server, Solver, load)
+                    REFINE_RELIABLE, REFINE_RESTART, UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Server, Solver, load)

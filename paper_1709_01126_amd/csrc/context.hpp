@@ -50,8 +50,9 @@ struct pot3d_ctx {
     float *r32 = nullptr, *p32[2] = {nullptr, nullptr}, *e32 = nullptr;
     DevScalars *sc32 = nullptr;
     hipGraphExec_t graph32 = nullptr;
-    double inner_tol = 1e-4;
+    double inner_tol = 0.0;   // 0: the mode's default
     int max_outer = 50;
+    int refine_mode = POT3D_REFINE_RELIABLE;
 
     bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;
@@ -107,8 +108,12 @@ int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMem
 int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit);
 // Refined: r = b - A x in FP64 and the outer test; waits, then *out holds the scalars.
 int refined_outer_check(pot3d_ctx *c, hipStream_t s, DevScalars *out);
-// Refined: normalised FP32 residual, e = 0, and the inner PCG start.
-int refined_start_inner(pot3d_ctx *c, hipStream_t s, double tol, int maxit_left, double outer_relres);
+// Refined: normalised FP32 residual, e = 0, and the inner PCG start (a
+// restart, or in reliable-update mode the continuation of the previous
+// segment `prev`, which ran in normalisation scale_prev).  outer: the scalars
+// of the outer check just made.
+int refined_start_inner(pot3d_ctx *c, hipStream_t s, double tol, int maxit_left, const DevScalars &outer,
+                        const DevScalars *prev, double scale_prev);
 // Refined: x += ||r|| e.
 int refined_correct(pot3d_ctx *c, hipStream_t s);
 // True residual, pole values, Phi out, statistics; returns the solve status.

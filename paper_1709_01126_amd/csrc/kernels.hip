@@ -771,7 +771,8 @@ __device__ __forceinline__ void block_sums(const double *partial, int nb, int nc
 __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const double *partial, int nb)
 {
     // the start-of-solve and end-of-solve finishers run whatever the done flag says
-    const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner;
+    const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner ||
+                        which == kFinResume;
     if (!always && sc->done) return;
     double s[3] = {0.0, 0.0, 0.0};
     const int ncomp = (which == kFinSigma) ? 1 : ((which == kFinInit || which == kFinOuter) ? 3 : 2);
@@ -876,14 +877,20 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
                 sc->status = POT3D_ENOCONV;
             }
         }
-    } else {  // kFinInner: PCG start on the normalised FP32 residual (e = 0, r = r32)
+    } else {
+        // kFinInner: PCG start on the normalised FP32 residual (e = 0, p = 0,
+        // r = r32).  kFinResume: the same residual replacement, but the last
+        // search direction is kept (rescaled to the new normalisation), and
+        // beta = rho_new / rho_prev continues the recurrence; the host leaves
+        // 1 / rho_prev (in the new units) in sc->scale.
         const double rnorm = sqrt(s[1]);
+        const double beta = (which == kFinResume) ? s[0] * sc->scale : 0.0;
         sc->rho = s[0];
         sc->rr = s[1];
         sc->bb = s[1];
         sc->bnorm = rnorm;
         sc->alpha = 0.0;
-        sc->beta = 0.0;
+        sc->beta = beta;
         sc->k = 0;
         sc->zero_solution = 0;
         sc->relres = 1.0;
@@ -919,6 +926,20 @@ __global__ void cast_residual_kernel(const double *r64, float *r32, float *e32, 
         r32[q] = (float)(r64[q] * scale);
         e32[q] = 0.0f;
         p32[q] = 0.0f;
+    }
+}
+
+// Reliable update of the FP32 inner iteration: the true residual replaces the
+// recursive one, the correction restarts from zero, and the last search
+// direction continues in the new units (pdst = f psrc; the two may alias).
+__global__ void resume_residual_kernel(const double *r64, float *r32, float *e32, const float *psrc, float *pdst,
+                                       long long n, const DevScalars *sc, float f)
+{
+    const double scale = sc->scale;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        r32[q] = (float)(r64[q] * scale);
+        e32[q] = 0.0f;
+        pdst[q] = f * psrc[q];
     }
 }
 
@@ -1259,6 +1280,13 @@ hipError_t launch_cast_residual(const double *r64, float *r32, float *e32, float
                                 const DevScalars *sc, hipStream_t s)
 {
     cast_residual_kernel<<<stream_blocks(npad), 256, 0, s>>>(r64, r32, e32, p32, npad, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_resume_residual(const double *r64, float *r32, float *e32, const float *psrc, float *pdst,
+                                  long long npad, const DevScalars *sc, float f, hipStream_t s)
+{
+    resume_residual_kernel<<<stream_blocks(npad), 256, 0, s>>>(r64, r32, e32, psrc, pdst, npad, sc, f);
     return hipGetLastError();
 }
 

@@ -12,7 +12,8 @@ enum FinWhich : int {
     kFinRho = 2,    // after update-r: convergence test, beta
     kFinTrue = 3,   // after a residual pass without store: true relative residual
     kFinOuter = 4,  // refinement, after the FP64 residual pass: outer test, scale = 1/||r||
-    kFinInner = 5   // refinement, after the r.z pass on the FP32 residual: inner start
+    kFinInner = 5,  // refinement, after the r.z pass on the FP32 residual: inner start
+    kFinResume = 6  // refinement, reliable update: as kFinInner, keeping the direction
 };
 
 // Stencil kernel shapes.  march: TJ x 64 tile per workgroup with an LDS plane;
@@ -64,6 +65,9 @@ hipError_t launch_repack(const double *src, double *dst, long long nrows, int np
 // r32 = float(r64 * sc->scale); e32 = 0; p32 = 0 (all npad elements)
 hipError_t launch_cast_residual(const double *r64, float *r32, float *e32, float *p32, long long npad,
                                 const DevScalars *sc, hipStream_t s);
+// r32 = float(r64 * sc->scale); e32 = 0; pdst = f * psrc (all npad elements; pdst may be psrc)
+hipError_t launch_resume_residual(const double *r64, float *r32, float *e32, const float *psrc, float *pdst,
+                                  long long npad, const DevScalars *sc, float f, hipStream_t s);
 // x64 += double(e32) / sc->scale (all npad elements)
 hipError_t launch_add_correction(double *x64, const float *e32, long long npad, const DevScalars *sc, hipStream_t s);
 // per-workgroup partials of r.z and r.r (z = D^-1 r) for an FP32 vector; nblocks <= cap

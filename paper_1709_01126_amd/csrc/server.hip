@@ -67,6 +67,8 @@ struct Slot {
     bool active = false;
     int total_inner = 0, outer = 0, launches = 0;
     unsigned phase = 0;   // bumped whenever the slot's solve (re)starts on the device
+    DevScalars last_inner{};   // refined: scalars of the inner segment that just ended
+    double scale_prev = 0.0;   // refined: the normalisation that segment ran in
 };
 
 // What a queued replay covered: per slot, the request and phase at launch.
@@ -381,7 +383,9 @@ int refined_advance(pot3d_server *sv, Slot &sl)
         out.status = POT3D_ENOCONV;
         return retire(sv, sl, out, sl.total_inner, sl.outer);
     }
-    SV_CALL(sv, c, refined_start_inner(c, sv->stream, r->tol, r->maxit - sl.total_inner, out.relres));
+    SV_CALL(sv, c, refined_start_inner(c, sv->stream, r->tol, r->maxit - sl.total_inner, out,
+                                       sl.outer > 0 ? &sl.last_inner : nullptr, sl.scale_prev));
+    sl.scale_prev = out.scale;
     sl.phase = ++sv->next_phase;
     return POT3D_OK;
 }
@@ -575,6 +579,7 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
             }
             sl.total_inner += st.k;
             sl.outer += 1;
+            sl.last_inner = st;
             if (st.status == POT3D_EBREAKDOWN) {
                 DevScalars out = st;
                 out.status = POT3D_EBREAKDOWN;

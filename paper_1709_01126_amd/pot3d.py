@@ -19,11 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libpot3d_checked.so" if os.environ.get("POT3D_LI
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 UPPER_SOURCE_SURFACE, UPPER_CLOSED_WALL = 0, 1
 FP64, FP32_REFINED = 0, 1
+REFINE_RESTART, REFINE_RELIABLE = 0, 1
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
                 EBREAKDOWN: "EBREAKDOWN"}
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
-            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement", "pot3d_destroy",
+            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
+            "pot3d_set_refinement_mode", "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
             "pot3d_server_set_cache_budget", "pot3d_server_get_stats", "pot3d_server_destroy",
@@ -94,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_time_kernels.restype = i
     lib.pot3d_set_refinement.argtypes = [vp, ctypes.c_double, i]
     lib.pot3d_set_refinement.restype = i
+    lib.pot3d_set_refinement_mode.argtypes = [vp, i]
+    lib.pot3d_set_refinement_mode.restype = i
     lib.pot3d_destroy.argtypes = [vp]
     lib.pot3d_destroy.restype = None
     lib.pot3d_last_error.argtypes = [vp]
@@ -207,6 +211,10 @@ def pot3d_set_refinement(ctx, inner_tol, max_outer):
     return load().pot3d_set_refinement(ctx, float(inner_tol), int(max_outer))
 
 
+def pot3d_set_refinement_mode(ctx, mode):
+    return load().pot3d_set_refinement_mode(ctx, int(mode))
+
+
 def pot3d_destroy(ctx):
     if ctx:
         load().pot3d_destroy(ctx)
@@ -282,6 +290,9 @@ class Solver:
 
     def set_refinement(self, inner_tol, max_outer=50):
         self._check(pot3d_set_refinement(self.ctx, inner_tol, max_outer), (OK,))
+
+    def set_refinement_mode(self, mode):
+        self._check(pot3d_set_refinement_mode(self.ctx, mode), (OK,))
 
     def close(self):
         if self.ctx:

@@ -122,3 +122,37 @@ def test_refined_full_size_bipole_151x301x601():
     assert st == P.OK
     assert tr <= w.tol * 1.01
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("case", [GRIDS[4], GRIDS[6]], ids=label)
+def test_refinement_modes(case):
+    """Restart (plain defect correction) and reliable updates (the search
+    direction continues across FP64 residual replacements) both reach the
+    FP64 residual; reliable updates need no more iterations than restarts.
+    A too-small reliable-update tolerance is bounded by the segment cap."""
+    rf, tf, pf = make_faces(*case)
+    br = magnetograms.br_bipoles(tf, pf, 40, seed=9)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000)
+    its = {}
+    for name, mode, itol in (("restart", P.REFINE_RESTART, None), ("reliable", P.REFINE_RELIABLE, None),
+                             ("reliable-1e-4", P.REFINE_RELIABLE, 1e-4)):
+        with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+            s.set_refinement_mode(mode)
+            if itol is not None:
+                s.set_refinement(itol, 50)
+            phi, st, it, rr = refined_solve(s, br, tol, 200_000)
+            outer = s.stats()["outer"]
+        tr = oracle.true_relres(ref["coef"], ref["b"], phi)
+        e2 = np.linalg.norm(phi - ref["phi"]) / np.linalg.norm(ref["phi"])
+        print(f"[refined modes] {label(case)} {name}: inner iters {it} outer {outer} (fp64 oracle {ref['iters']}) "
+              f"true_relres {tr:.2e} err2 {e2:.2e}", flush=True)
+        assert st == P.OK and tr <= tol * 1.01 and e2 <= 1e-7
+        its[name] = it
+    assert its["reliable"] <= its["restart"] * 1.05
+    assert its["reliable-1e-4"] <= 4 * its["restart"]
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        with pytest.raises(P.Pot3dError):
+            s.set_refinement_mode(7)
+    with P.Solver(rf, tf, pf) as s64:
+        assert P.pot3d_set_refinement_mode(s64.ctx, P.REFINE_RELIABLE) == P.EINVAL
