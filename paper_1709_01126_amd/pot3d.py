@@ -74,6 +74,13 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1709_01126_amd.build` "
                           "(or __graft_entry__.build()); there is no CPU fallback")
+    # torch ships its own HIP runtime.  If it is used in this process it must be
+    # loaded first, so that the library binds to the same runtime instead of
+    # loading a second one (two runtimes in one process do not share devices).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     d = ctypes.POINTER(ctypes.c_double)
     vp = ctypes.c_void_p
