@@ -16,6 +16,7 @@ using pot3d::DevScalars;
 using pot3d::GridArgs;
 using pot3d::RowCoef;
 using pot3d::StencilVecs;
+using pot3d::kTileMarch16;
 using pot3d::kTileMarch8;
 using pot3d::kTileWave2;
 
@@ -24,7 +25,7 @@ struct pot3d_ctx {
     int nr = 0, nt = 0, np = 0, pitch = 0;
     long long n = 0, npad = 0;
     int precision = POT3D_FP64;
-    int tile_p = kTileMarch8, tile_r = kTileWave2, tile_o = kTileWave2;
+    int tile_p = kTileMarch16, tile_r = kTileMarch8, tile_o = kTileWave2;   // set by choose_launch
     int max_blocks = 0;
     int num_cu = 256;
     int graph_m = 16;

@@ -5,6 +5,7 @@ import math
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -129,3 +130,13 @@ def test_server_rejects_invalid_arguments():
     assert P.pot3d_server_get_stats(None)[0] == P.EINVAL
     assert P.pot3d_server_set_cache_budget(None, 1e9) == P.EINVAL
     P.pot3d_server_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU; asking for more exits with a message
+    before touching a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "one GPU" in res.stderr or "single device" in res.stderr
