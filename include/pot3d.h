@@ -270,11 +270,14 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
 /*
  * Queue one solve.  Faces, nr, nt, np and br as in pot3d_create and
  * pot3d_solve (host memory, copied); tol and maxit as in pot3d_solve.
- * *id receives the request id.  Only validates and copies; no device work.
+ * phi_out: host, nr*nt*np, where the server writes Phi when the solve
+ * retires (it must stay valid until the request is done), or NULL to let the
+ * server keep Phi until pot3d_server_result.  *id receives the request id.
+ * Only validates and copies; no device work.
  */
 int pot3d_server_submit(pot3d_server *sv, const double *r_faces, int nr, const double *t_faces, int nt,
                         const double *p_faces, int np, const double *br, double tol, int maxit,
-                        long long *id);
+                        double *phi_out, long long *id);
 
 /*
  * One scheduling step (retire, admit, one graph replay); returns after the
@@ -287,8 +290,9 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
 
 /*
  * State of request `id` into *info (may be NULL).  Once it is done and phi is
- * not NULL, Phi (host, nr*nt*np, phi-fastest) is copied out and the request
- * is forgotten; later calls with its id return POT3D_EINVAL.
+ * not NULL, Phi (host, nr*nt*np, phi-fastest) is copied into phi (no copy if
+ * phi is the submit-time phi_out, which already holds it) and the request is
+ * forgotten; later calls with its id return POT3D_EINVAL.
  */
 int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_request_info *info);
 

@@ -24,8 +24,8 @@
 // slot that finished in replay k runs through replay k+1 as a no-op, and
 // retirement and admission are ordered after it on the same stream.
 // The graphs read the slot tables at run time, so requests join and leave
-// between replays without recapture; one graph is captured per launch width
-// (a power of two of workgroups) the first time a batch needs it.  Every slot
+// between replays without recapture; one graph is captured per pair of launch
+// widths the first time a batch needs it.  Every slot
 // runs exactly the launch shape, tile order and reduction order of a single
 // solve on the same grid, so each result is bitwise the one the request gets
 // from pot3d_solve.
@@ -54,7 +54,8 @@ struct Request {
     std::vector<double> rf, tf, pf, br;
     double tol = 0.0;
     int maxit = 0;
-    std::vector<double> phi;
+    double *phi_out = nullptr;                 // caller's buffer (from submit), or NULL
+    std::unique_ptr<double[]> phi_buf;         // otherwise Phi is kept here until taken
     int status = POT3D_OK, iters = 0, outer = 0;
     double relres_true = 0.0;
     double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
@@ -69,6 +70,13 @@ struct Slot {
     unsigned phase = 0;   // bumped whenever the slot's solve (re)starts on the device
     DevScalars last_inner{};   // refined: scalars of the inner segment that just ended
     double scale_prev = 0.0;   // refined: the normalisation that segment ran in
+};
+
+// A captured batched graph: launch widths of the two passes, last use.
+struct BatchGraph {
+    int wp = 0, wr = 0;
+    unsigned long long last_use = 0;
+    hipGraphExec_t exec = nullptr;
 };
 
 // What a queued replay covered: per slot, the request and phase at launch.
@@ -107,8 +115,9 @@ struct pot3d_server {
     DevScalars *h_status = nullptr;   // pinned, [2][slot]: statuses after the two latest replays
     Replay replay[2];
     int last = -1;                    // replay buffer of the most recent launch
-    std::vector<std::pair<int, hipGraphExec_t>> graphs;   // (workgroups per launch, graph), widening
-    int need_blocks = 0;   // workgroups the active slots occupy (max over the two passes)
+    std::vector<BatchGraph> graphs;   // captured batched graphs by launch widths
+    unsigned long long graph_clock = 0;
+    int need_p = 0, need_r = 0;   // workgroups the active slots own in each pass
     std::chrono::steady_clock::time_point t0;
     std::string err;
 
@@ -147,16 +156,16 @@ hipError_t dalloc(T **p, size_t count)
 }
 
 template <typename V>
-int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr, int width,
+int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr, int wp, int wr,
                     hipGraphExec_t *out)
 {
     hipStream_t s = sv->capture_stream;
     SV_TRY(sv, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int it = 0; it < sv->graph_m && e == hipSuccess; ++it) {
-        e = launch_stencil_batch<V>(kUpdateP, sv->tile_p, dp[it & 1], sv->max_slots, width, s);
+        e = launch_stencil_batch<V>(kUpdateP, sv->tile_p, dp[it & 1], sv->max_slots, wp, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinSigma, sv->d_finp, sv->max_slots, s);
-        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, sv->tile_r, dr[it & 1], sv->max_slots, width, s);
+        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, sv->tile_r, dr[it & 1], sv->max_slots, wr, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinRho, sv->d_finr, sv->max_slots, s);
     }
     hipGraph_t graph = nullptr;
@@ -172,26 +181,35 @@ int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *con
     return POT3D_OK;
 }
 
-// The narrowest captured graph that covers `need` workgroups, capturing one
-// (a power of two of at least 1024) if none does.
-int graph_for(pot3d_server *sv, int need, hipGraphExec_t *out)
+// The graph whose passes launch exactly the workgroups the active slots own
+// (wp for the p update, wr for the r/x update), captured on first need, so
+// that no launch carries idle workgroups.  At most kMaxGraphs are kept; the
+// least recently used one goes first.
+constexpr size_t kMaxGraphs = 64;
+
+int graph_for(pot3d_server *sv, int wp, int wr, hipGraphExec_t *out)
 {
-    for (const auto &w : sv->graphs)
-        if (w.first >= need) {
-            *out = w.second;
+    for (size_t q = 0; q < sv->graphs.size(); ++q) {
+        if (sv->graphs[q].wp == wp && sv->graphs[q].wr == wr) {
+            sv->graphs[q].last_use = ++sv->graph_clock;
+            *out = sv->graphs[q].exec;
             return POT3D_OK;
         }
-    int width = 1024;
-    while (width < need) width *= 2;
+    }
+    if (sv->graphs.size() >= kMaxGraphs) {
+        size_t oldest = 0;
+        for (size_t q = 1; q < sv->graphs.size(); ++q)
+            if (sv->graphs[q].last_use < sv->graphs[oldest].last_use) oldest = q;
+        // the stream may still replay it: wait before destroying
+        SV_TRY(sv, hipStreamSynchronize(sv->stream));
+        (void)hipGraphExecDestroy(sv->graphs[oldest].exec);
+        sv->graphs.erase(sv->graphs.begin() + oldest);
+    }
     hipGraphExec_t g = nullptr;
-    const int rc = sv->precision == POT3D_FP64 ? capture_batched<double>(sv, sv->d_p64, sv->d_r64, width, &g)
-                                               : capture_batched<float>(sv, sv->d_p32, sv->d_r32, width, &g);
+    const int rc = sv->precision == POT3D_FP64 ? capture_batched<double>(sv, sv->d_p64, sv->d_r64, wp, wr, &g)
+                                               : capture_batched<float>(sv, sv->d_p32, sv->d_r32, wp, wr, &g);
     if (rc != POT3D_OK) return rc;
-    sv->graphs.emplace_back(width, g);
-    std::sort(sv->graphs.begin(), sv->graphs.end(),
-              [](const std::pair<int, hipGraphExec_t> &a, const std::pair<int, hipGraphExec_t> &b) {
-                  return a.first < b.first;
-              });
+    sv->graphs.push_back(BatchGraph{wp, wr, ++sv->graph_clock, g});
     *out = g;
     return POT3D_OK;
 }
@@ -253,7 +271,8 @@ void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<Ba
         offp += round_up(c->grid_p.nblocks, kBlockAlign);
         offr += round_up(c->grid_r.nblocks, kBlockAlign);
     }
-    sv->need_blocks = std::max(offp, offr);
+    sv->need_p = offp;
+    sv->need_r = offr;
 }
 
 int upload_tables(pot3d_server *sv)
@@ -360,11 +379,15 @@ int retire(pot3d_server *sv, Slot &sl, DevScalars fin, int total_iters, int oute
 {
     pot3d_ctx *c = sl.ctx;
     Request *r = sl.req;
-    r->phi.resize((size_t)r->nr * r->nt * r->np);
+    double *dst = r->phi_out;
+    if (!dst) {
+        r->phi_buf.reset(new double[(size_t)r->nr * r->nt * r->np]);
+        dst = r->phi_buf.get();
+    }
     int iters = 0;
     double rel = 0.0;
     SV_TRY(sv, hipEventRecord(c->ev_loop1, sv->stream));
-    const int rc = finish_solve(c, r->phi.data(), hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
+    const int rc = finish_solve(c, dst, hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
                                 sv->precision == POT3D_FP32_REFINED ? 32.0 : 64.0, &iters, &rel);
     if (rc != POT3D_OK && rc != POT3D_ENOCONV && rc != POT3D_EBREAKDOWN) return sfail(sv, rc, pot3d_last_error(c));
     complete(sv, sl, rc, iters, outer, rel);
@@ -486,9 +509,9 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
         g_server_error = p->err;
         return bail(POT3D_EDEVICE);
     }
-    // the graph for the narrowest width, so that capture problems show here
+    // one graph now, so that capture problems show here
     hipGraphExec_t g0 = nullptr;
-    const int rc = graph_for(p, 1, &g0);
+    const int rc = graph_for(p, kBlockAlign, kBlockAlign, &g0);
     if (rc != POT3D_OK) {
         g_server_error = p->err;
         return bail(rc);
@@ -498,7 +521,8 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
 }
 
 int pot3d_server_submit(pot3d_server *sv, const double *r_faces, int nr, const double *t_faces, int nt,
-                        const double *p_faces, int np, const double *br, double tol, int maxit, long long *id)
+                        const double *p_faces, int np, const double *br, double tol, int maxit, double *phi_out,
+                        long long *id)
 {
     if (!sv) return sfail(nullptr, POT3D_EINVAL, "server is NULL");
     if (!id || !br) return sfail(sv, POT3D_EINVAL, "br and id are required");
@@ -518,6 +542,7 @@ int pot3d_server_submit(pot3d_server *sv, const double *r_faces, int nr, const d
     r->br.assign(br, br + (size_t)nt * np);
     r->tol = tol;
     r->maxit = maxit;
+    r->phi_out = phi_out;
     r->t_submit = sv->now();
     *id = r->id;
     sv->queue.push_back(r.get());
@@ -540,7 +565,7 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
     if (active > 0) {
         const int b = prev == 0 ? 1 : 0;
         hipGraphExec_t g = nullptr;
-        const int rc = graph_for(sv, sv->need_blocks, &g);
+        const int rc = graph_for(sv, sv->need_p, sv->need_r, &g);
         if (rc != POT3D_OK) return rc;
         SV_TRY(sv, hipGraphLaunch(g, s));
         ++sv->replays;
@@ -659,7 +684,9 @@ int pot3d_server_result(pot3d_server *sv, long long id, double *phi, pot3d_reque
         info->t_done = r->t_done;
     }
     if (r->done && phi) {
-        if (!r->phi.empty()) std::memcpy(phi, r->phi.data(), r->phi.size() * sizeof(double));
+        const size_t n = (size_t)r->nr * r->nt * r->np;
+        const double *src = r->phi_out ? r->phi_out : r->phi_buf.get();
+        if (src && src != phi) std::memcpy(phi, src, n * sizeof(double));
         sv->requests.erase(it);
     }
     return POT3D_OK;
@@ -699,7 +726,7 @@ void pot3d_server_destroy(pot3d_server *sv)
         if (sl.ctx) free_ctx(sl.ctx);
     for (pot3d_ctx *c : sv->idle) free_ctx(c);
     for (auto &g : sv->graphs)
-        if (g.second) (void)hipGraphExecDestroy(g.second);
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     void *bufs[] = {sv->d_p64[0], sv->d_p64[1], sv->d_r64[0], sv->d_r64[1], sv->d_p32[0], sv->d_p32[1],
                     sv->d_r32[0], sv->d_r32[1], sv->d_finp, sv->d_finr};
     for (void *b : bufs)

@@ -114,7 +114,7 @@ def load(path: str = LIB_PATH):
     ll = ctypes.c_longlong
     lib.pot3d_server_create.argtypes = [i, i, i, ctypes.c_double, ctypes.POINTER(vp)]
     lib.pot3d_server_create.restype = i
-    lib.pot3d_server_submit.argtypes = [vp, d, i, d, i, d, i, d, ctypes.c_double, i, ctypes.POINTER(ll)]
+    lib.pot3d_server_submit.argtypes = [vp, d, i, d, i, d, i, d, ctypes.c_double, i, d, ctypes.POINTER(ll)]
     lib.pot3d_server_submit.restype = i
     lib.pot3d_server_step.argtypes = [vp, ctypes.POINTER(i), ctypes.POINTER(i), ctypes.POINTER(ll)]
     lib.pot3d_server_step.restype = i
@@ -331,12 +331,13 @@ def pot3d_server_create(device=0, precision=FP64, max_slots=8, hbm_budget_bytes=
     return st, (out.value if st == OK else None)
 
 
-def pot3d_server_submit(sv, r_faces, t_faces, p_faces, br, tol, maxit):
-    """Returns (status, request id)."""
+def pot3d_server_submit(sv, r_faces, t_faces, p_faces, br, tol, maxit, phi_out=None):
+    """phi_out: None, or a float64 array of N that receives Phi at retirement
+    (keep it alive until the request is done).  Returns (status, request id)."""
     rf, tf, pf, br = _f64(r_faces), _f64(t_faces), _f64(p_faces), _f64(br)
     rid = ctypes.c_longlong(0)
     st = load().pot3d_server_submit(sv, _dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1, _dp(br),
-                                    float(tol), int(maxit), ctypes.byref(rid))
+                                    float(tol), int(maxit), _dp(phi_out), ctypes.byref(rid))
     return st, rid.value
 
 
@@ -377,16 +378,19 @@ class Server:
         if st != OK:
             raise Pot3dError(st, pot3d_server_last_error(None))
         self.sv = sv
-        self.shapes = {}
+        self.outputs = {}   # request id -> the array Phi is written into
 
     def _check(self, st):
         if st != OK:
             raise Pot3dError(st, pot3d_server_last_error(self.sv))
 
     def submit(self, r_faces, t_faces, p_faces, br, tol, maxit):
-        st, rid = pot3d_server_submit(self.sv, r_faces, t_faces, p_faces, br, tol, maxit)
+        """Queue a solve; Phi is written straight into an array the server
+        object holds until take()."""
+        phi = np.empty((len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1))
+        st, rid = pot3d_server_submit(self.sv, r_faces, t_faces, p_faces, br, tol, maxit, phi)
         self._check(st)
-        self.shapes[rid] = (len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1)
+        self.outputs[rid] = phi
         return rid
 
     def step(self):
@@ -402,12 +406,12 @@ class Server:
 
     def take(self, rid):
         """Phi and info of a finished request (which the server then forgets)."""
-        phi = np.empty(self.shapes[rid])
+        phi = self.outputs[rid]
         st, info = pot3d_server_result(self.sv, rid, phi)
         self._check(st)
         if not info["done"]:
             raise Pot3dError(EINVAL, f"request {rid} is not done")
-        del self.shapes[rid]
+        del self.outputs[rid]
         return phi, info
 
     def set_cache_budget(self, nbytes):
