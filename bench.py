@@ -58,8 +58,14 @@ def load_traffic(workload: str, kernel: str):
     return None if k is None else k.get("hbm_bytes_per_launch")
 
 
+# algorithmic bytes per unknown of each iteration kernel, and the kernel-name
+# fragment that identifies it in a trace
+KERNEL_KEYS = {"sweep": (48.0, "stencil_sweep<"), "update_p": (24.0, ", 2, double>"),
+               "update_r": (40.0, ", 3, double>")}
+
+
 def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
-    """HBM bytes per launch of the two iteration kernels from FETCH_SIZE and
+    """HBM bytes per launch of the iteration kernels from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for the device copy of N doubles in the same run (known bytes / counter)."""
     import csv
@@ -85,14 +91,17 @@ def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
     f_scale = 8.0 * n / copy_fetch
     w_scale = 8.0 * n / copy_write
     kernels = {}
-    for key, mode in (("update_p", ", 2, double>"), ("update_r", ", 3, double>")):
-        name = [k for k in fetch if "stencil_" in k and mode in k][0]
+    for key, (per_unknown, frag) in KERNEL_KEYS.items():
+        names = [k for k in fetch if "stencil_" in k and frag in k and "double" in k]
+        if not names:
+            continue
+        name = names[0]
         # dispatches that ran (the graph's launches after convergence return at once)
         real_f = [x for x in fetch[name] if x > 0.1 * max(fetch[name])]
         real_w = [x for x in write[name] if x > 0.1 * max(write[name])]
         fb = statistics.median(real_f) * f_scale
         wb = statistics.median(real_w) * w_scale
-        alg = (24.0 if key == "update_p" else 40.0) * n
+        alg = per_unknown * n
         kernels[key] = {"kernel": name.split("(")[0], "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                         "hbm_bytes_per_launch": fb + wb, "alg_bytes_per_launch": alg,
                         "traffic_over_alg": (fb + wb) / alg}
@@ -107,6 +116,8 @@ def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
 
 
 def kernel_name(stats, which):
+    if which == "sweep":
+        return f"stencil_sweep<{stats['sweep_rows']},double>"
     tile = stats["tile_p"] if which == "update_p" else stats["tile_r"]
     mode = 2 if which == "update_p" else 3
     if tile > 100:
@@ -334,8 +345,13 @@ def main():
     maxit = 500_000
 
     if args.profile_kernels:
+        # both iteration forms: the one-sweep kernel, then the two passes
+        solver.solve_device(d_br, d_phi, 0.0, 8)
+        ms_s, _ = solver.time_kernels(args.kernel_reps)
+        solver.set_iteration(pot3d.ITER_TWO_PASS)
         solver.solve_device(d_br, d_phi, 0.0, 8)
         ms_p, ms_r = solver.time_kernels(args.kernel_reps)
+        solver.set_iteration(pot3d.ITER_ONE_SWEEP)
         # counter calibration: a device copy of N doubles whose source is not in
         # the 256 MB memory-side cache (a 1 GB fill runs in between)
         src = torch.ones(w.n, dtype=torch.float64, device=dev)
@@ -345,7 +361,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del flush
-        print(json.dumps({"profile_kernels": w.describe(), "update_p_ms": ms_p, "update_r_ms": ms_r,
+        print(json.dumps({"profile_kernels": w.describe(), "sweep_ms": ms_s, "update_p_ms": ms_p, "update_r_ms": ms_r,
                           "copy_bytes_each_way": 8 * w.n, "launch": solver.stats()}), flush=True)
         solver.close()
         return
@@ -373,13 +389,18 @@ def main():
     phi_norm = float(torch.linalg.vector_norm(d_phi).item())
 
     it_per_s = total_iters / elapsed
-    bytes_iter = 64.0 * w.n
-    # per-kernel average launch time on the context stream (hipEvents)
-    ms_p, ms_r = solver.time_kernels(args.kernel_reps)
-    kern = {
-        "update_p": {"alg_bytes_per_launch": 24.0 * w.n, "ms": ms_p},
-        "update_r": {"alg_bytes_per_launch": 40.0 * w.n, "ms": ms_r},
-    }
+    one_sweep = stats["iteration"] == pot3d.ITER_ONE_SWEEP
+    bytes_iter = stats["bytes_per_iter"]
+    # per-kernel average launch time as the kernels run in a solve
+    # (device wall-clock stamps per launch inside a replayed graph)
+    ms_a, ms_b = solver.time_kernels(args.kernel_reps)
+    if one_sweep:
+        kern = {"sweep": {"alg_bytes_per_launch": KERNEL_KEYS["sweep"][0] * w.n, "ms": ms_a}}
+    else:
+        kern = {
+            "update_p": {"alg_bytes_per_launch": KERNEL_KEYS["update_p"][0] * w.n, "ms": ms_a},
+            "update_r": {"alg_bytes_per_launch": KERNEL_KEYS["update_r"][0] * w.n, "ms": ms_b},
+        }
     for k, v in kern.items():
         v["gbs"] = v["alg_bytes_per_launch"] / (v["ms"] * 1e-3) / 1e9
     dom = max(kern, key=lambda k: kern[k]["ms"])
@@ -411,11 +432,25 @@ def main():
         "fp64_solve_s": round(elapsed / args.steps, 4),
         "kernels": {k: {"ms": round(v["ms"], 4), "gbs_alg": round(v["gbs"], 1)} for k, v in kern.items()},
         "loop_us_per_iter": round(loop_ms * 1e3 / max(1, total_iters), 2),
-        "launch": {k: stats[k] for k in ("tile_p", "tile_r", "chunk_p", "chunk_r", "blocks_p", "blocks_r", "pitch")},
+        "iteration": "one-sweep" if one_sweep else "two-pass",
+        "launch": ({k: stats[k] for k in ("sweep_rows", "chunk_s", "blocks_s", "pitch")} if one_sweep else
+                   {k: stats[k] for k in ("tile_p", "tile_r", "chunk_p", "chunk_r", "blocks_p", "blocks_r", "pitch")}),
         "status": [pot3d.STATUS_NAMES.get(s, s) for s in statuses],
         "relres_true": stats["relres_true"],
         "phi_l2": phi_norm,
     }
+    if one_sweep:
+        # the two-pass form of the same FP64 iteration, one solve, for comparison
+        solver.set_iteration(pot3d.ITER_TWO_PASS)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st2, it2, rr2 = solver.solve_device(d_br, d_phi, w.tol, maxit)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter() - t0
+        result["two_pass"] = {"iters_per_s": round(it2 / t2, 2), "iters": it2, "solve_s": round(t2, 4),
+                              "status": pot3d.STATUS_NAMES.get(st2, st2), "relres_true": rr2}
+        print(f"[bench] two-pass: {it2 / t2:.1f} it/s ({it2} iters)", file=sys.stderr, flush=True)
+        solver.set_iteration(pot3d.ITER_ONE_SWEEP)
     if not args.no_refined:
         # FP32-refined solves of the same problem to the same FP64 residual
         phi64 = d_phi.clone()

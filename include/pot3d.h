@@ -68,6 +68,17 @@ enum pot3d_refine_mode {
                                    direction after the FP64 residual replacement (default)     */
 };
 
+enum pot3d_iteration {
+    POT3D_ITER_TWO_PASS = 0,   /* two sweeps over memory per PCG iteration: the direction
+                                  update with A p and p.Ap, then the r/x update with r.z and
+                                  r.r (64 bytes per unknown)                                 */
+    POT3D_ITER_ONE_SWEEP = 1   /* one sweep per iteration: the r/x update of iteration j-1
+                                  and the direction update of iteration j together, with
+                                  r.z of the next residual predicted from p.Ap, z.Ap and
+                                  Ap.D^-1 Ap (48 bytes per unknown).  The same PCG in exact
+                                  arithmetic.  Default for FP64 contexts.                   */
+};
+
 enum pot3d_precision {
     POT3D_FP64 = 0,          /* FP64 vectors, stencil and reductions throughout              */
     POT3D_FP32_REFINED = 1   /* FP32 inner PCG inside FP64 defect correction (see
@@ -84,8 +95,8 @@ typedef struct pot3d_stats {
     double relres_true;      /* ||b - A Phi||/||b||, recomputed in FP64 at exit             */
     double solve_ms;         /* wall time of the last solve call on the device             */
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
-    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 64 N (FP64), 32 N
-                                (FP32 inner)                                               */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 48 N (FP64, one
+                                sweep), 64 N (FP64, two passes), 32 N (FP32 inner)         */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -93,6 +104,9 @@ typedef struct pot3d_stats {
                                 cells; 102/104/108 = wavefront tile of 2/4/8 rows x 128   */
     int chunk_p, chunk_r;    /* radial layers per workgroup chunk, per pass                 */
     int blocks_p, blocks_r;  /* workgroups per launch, per pass                              */
+    int iteration;           /* POT3D_ITER_* of the last solve (two-pass in refined mode)   */
+    int sweep_rows;          /* one-sweep kernel: tile box rows per wavefront (4, 6 or 8)   */
+    int chunk_s, blocks_s;   /* one-sweep kernel: radial layers per chunk, workgroups      */
 } pot3d_stats;
 
 /*
@@ -103,7 +117,8 @@ typedef struct pot3d_stats {
  *   nr >= 2, nt >= 2, np >= 3.  Arrays are host memory, copied.
  *   upper_bc   POT3D_UPPER_SOURCE_SURFACE (closed wall is rejected with POT3D_EINVAL)
  *   precision  POT3D_FP64 or POT3D_FP32_REFINED
- * On success *out owns device buffers of about 32 N + (FP32 mode) 16 N bytes.
+ * On success *out owns device buffers of about 40 N bytes (FP64) or 32 N + 16 N
+ * bytes (FP32-refined).
  */
 int pot3d_create(const double *r_faces, int nr,
                  const double *t_faces, int nt,
@@ -163,14 +178,16 @@ int pot3d_pole_values(const pot3d_ctx *ctx, double *north, double *south);
 int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
 
 /*
- * Benchmark helper: average duration in ms of the two per-iteration stencil
- * kernels (the p update with A p and p.Ap; the r/x update with r.z and r.r)
- * as they run in a solve: a graph of `reps` iterations in the solve's order
- * is replayed twice back to back on the context's stream, and in the second
- * replay each stencil launch records its first workgroup's start and its
- * last workgroup's end on the device wall clock.  FP32-refined
- * contexts time the FP32 inner kernels.  It runs on the vectors the context
- * holds and overwrites them; a later solve re-initializes everything.
+ * Benchmark helper: average duration in ms of the per-iteration stencil
+ * kernels as they run in a solve: a graph of `reps` iterations in the
+ * solve's order is replayed twice back to back on the context's stream, and
+ * in the second replay each stencil launch records its first workgroup's
+ * start and its last workgroup's end on the device wall clock.
+ * Two-pass iteration: *ms_update_p = the p update (A p, p.Ap), *ms_update_r =
+ * the r/x update (r.z, r.r).  One-sweep iteration: *ms_update_p = the sweep,
+ * *ms_update_r = 0.  FP32-refined contexts time the FP32 inner kernels (two
+ * passes).  It runs on the vectors the context holds and overwrites them; a
+ * later solve re-initializes everything.
  */
 int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
 
@@ -198,6 +215,15 @@ int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer);
  * POT3D_EINVAL for other contexts or modes.
  */
 int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
+
+/*
+ * FP64 contexts: the form of the PCG iteration (POT3D_ITER_ONE_SWEEP, the
+ * default, or POT3D_ITER_TWO_PASS; the environment variable POT3D_ITERATION
+ * = 0 or 1 sets the default of new contexts).  Both run the Jacobi-PCG of
+ * Sec. 2.3; their iterates agree to rounding.  FP32-refined contexts accept
+ * POT3D_ITER_TWO_PASS only.  POT3D_EINVAL otherwise.
+ */
+int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
 
 /* Free the context and all of its device memory.  NULL is a no-op. */
 void pot3d_destroy(pot3d_ctx *ctx);

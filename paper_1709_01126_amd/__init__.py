@@ -6,5 +6,5 @@ kernels are in ``csrc/`` and its interface is in ``include/pot3d.h``.
 ``pot3d`` is the ctypes binding.  PyTorch is only used by callers for device
 buffers and streams.
 """
-from .pot3d import (EBREAKDOWN, EDEVICE, EINVAL, ENOCONV, ENOMEM, FP32_REFINED, FP64, OK,  # noqa: F401
-                    REFINE_RELIABLE, REFINE_RESTART, UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Server, Solver, load)
+from .pot3d import (EBREAKDOWN, EDEVICE, EINVAL, ENOCONV, ENOMEM, FP32_REFINED, FP64, ITER_ONE_SWEEP,  # noqa: F401
+                    ITER_TWO_PASS, OK, REFINE_RELIABLE, REFINE_RESTART, UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Server, Solver, load)

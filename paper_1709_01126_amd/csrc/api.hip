@@ -164,6 +164,42 @@ GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed = 0)
     return g;
 }
 
+// Launch shape of the one-sweep kernel (`rows` box rows per wavefront):
+// tiles of tj x tk interior cells, tj <= 4 rows - 4 balanced over the polar
+// rows, tk = 48 cells by default (a multiple of 16, so a tile's stores cover
+// whole 128-byte lines), radial chunks sized for about `target` workgroups.
+// POT3D_SWEEP_TK and POT3D_SWEEP_CI override.
+GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target)
+{
+    const int tjmax = 4 * rows - 4;
+    const int tj = (c->nt + (c->nt + tjmax - 1) / tjmax - 1) / ((c->nt + tjmax - 1) / tjmax);
+    const int ntj = (c->nt + tj - 1) / tj;   // every tile starts inside the grid
+    const int tk = std::max(1, std::min(60, env_int("POT3D_SWEEP_TK", 48)));
+    const int ntk = (c->np + tk - 1) / tk;
+    const long long tiles = (long long)ntj * ntk;
+    int ci = env_int("POT3D_SWEEP_CI", 0);
+    if (ci <= 0) {
+        long long want = std::max<long long>(1, std::min<long long>((long long)target / tiles, c->nr));
+        ci = (int)((c->nr + want - 1) / want);
+    }
+    ci = std::max(1, std::min(ci, c->nr));
+    GridArgs g{};
+    g.nr = c->nr;
+    g.nt = c->nt;
+    g.np = c->np;
+    g.pitch = c->pitch;
+    g.plane = (long long)c->nt * c->pitch;
+    g.ci = ci;
+    g.nchunk = (c->nr + ci - 1) / ci;
+    g.ntj = ntj;
+    g.ntk = ntk;
+    g.tj = tj;
+    g.tk = tk;
+    g.nblocks = (int)(tiles * g.nchunk);
+    g.npad = c->npad;
+    return g;
+}
+
 int valid_tile(int tile, int dflt)
 {
     switch (tile) {
@@ -219,6 +255,18 @@ bool streams_from_hbm(const pot3d_ctx *c)
     return (double)c->npad * sizeof(double) >= 512.0 * 1024 * 1024;
 }
 
+// The one-sweep kernel addresses a vector with 32-bit byte offsets.
+bool sweep_capable(const pot3d_ctx *c)
+{
+    return c->precision == POT3D_FP64 && !c->serving && (double)c->npad * sizeof(double) < 4294967296.0;
+}
+
+// FP64 single-solve contexts iterate in one sweep unless set otherwise.
+bool one_sweep(const pot3d_ctx *c)
+{
+    return c->graph_s && c->iteration == POT3D_ITER_ONE_SWEEP;
+}
+
 void choose_launch(pot3d_ctx *c)
 {
     const bool fp32 = c->precision == POT3D_FP32_REFINED;
@@ -244,6 +292,16 @@ void choose_launch(pot3d_ctx *c)
     c->grid_p.reverse = env_int("POT3D_REVERSE_P", 0) != 0;
     c->grid_r.reverse = env_int("POT3D_REVERSE_R", 1) != 0;
     c->max_blocks = std::max(c->grid_p.nblocks, std::max(c->grid_r.nblocks, c->grid_o.nblocks));
+    if (sweep_capable(c)) {
+        // one-sweep kernel: about one resident set of workgroups
+        const int rows = env_int("POT3D_SWEEP_ROWS", 4);
+        c->sweep_rows = valid_sweep_rows(rows) ? rows : 4;
+        const int ts = env_int("POT3D_TARGET_BLOCKS_S", 0);
+        const int resident = std::max(1, sweep_blocks_per_cu<double>(c->sweep_rows)) * std::max(1, c->num_cu);
+        c->grid_s = make_sweep_grid(c, c->sweep_rows, ts > 0 ? ts : resident);
+        c->grid_s.reverse = env_int("POT3D_REVERSE_S", 0) != 0;
+        c->max_blocks = std::max(c->max_blocks, c->grid_s.nblocks);
+    }
 }
 
 void fill_shape(const pot3d_ctx *c, pot3d_stats &st)
@@ -254,11 +312,15 @@ void fill_shape(const pot3d_ctx *c, pot3d_stats &st)
     st.chunk_r = c->grid_r.ci;
     st.blocks_p = c->grid_p.nblocks;
     st.blocks_r = c->grid_r.nblocks;
+    st.iteration = one_sweep(c) ? POT3D_ITER_ONE_SWEEP : POT3D_ITER_TWO_PASS;
+    st.sweep_rows = c->sweep_rows;
+    st.chunk_s = c->grid_s.ci;
+    st.blocks_s = c->grid_s.nblocks;
 }
 
 void set_tables(pot3d_ctx *c)
 {
-    for (GridArgs *g : {&c->grid_p, &c->grid_r, &c->grid_o}) {
+    for (GridArgs *g : {&c->grid_p, &c->grid_r, &c->grid_o, &c->grid_s}) {
         g->rows = c->rows;
         g->dphi = c->dphi;
         g->ih = c->ih;
@@ -315,10 +377,46 @@ int capture_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, DevScalars *sc, h
     return POT3D_OK;
 }
 
-// Replay `graph` until the scalar block `sc` reports done, keeping one graph
-// queued ahead of the poll.  Returns POT3D_OK or a HIP error status.
-int replay_until_done(pot3d_ctx *c, hipGraphExec_t graph, DevScalars *sc, hipStream_t s, int maxit, int *launches,
-                      DevScalars *final_out)
+// Capture 2 m sweeps of the one-sweep iteration (sweep, finisher) on the
+// idle context stream.  Sweep j reads r and p from buffer j mod 2 and writes
+// buffer (j + 1) mod 2; 2 m is even, so replays continue the alternation.
+int capture_sweeps(pot3d_ctx *c, hipGraphExec_t *out)
+{
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    double *rb[2] = {c->r, c->r2};
+    double *pb[2] = {c->p[0], c->p[1]};
+    for (int it = 0; it < 2 * c->graph_m && e == hipSuccess; ++it) {
+        SweepVecs<double> v{};
+        v.r_in = rb[it & 1];
+        v.r_out = rb[(it + 1) & 1];
+        v.p_old = pb[it & 1];
+        v.p_new = pb[(it + 1) & 1];
+        v.x = c->x;
+        v.sc = c->sc;
+        v.partial = c->partial;
+        e = launch_sweep<double>(c->sweep_rows, c->grid_s, v, s);
+        if (e == hipSuccess) e = launch_finish(kFinSweep, c->sc, c->partial, c->grid_s.nblocks, s);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, POT3D_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return POT3D_OK;
+}
+
+// Replay `graph` (`per_graph` iterations each) until the scalar block `sc`
+// reports done, keeping one graph queued ahead of the poll.  Returns
+// POT3D_OK or a HIP error status.
+int replay_until_done(pot3d_ctx *c, hipGraphExec_t graph, DevScalars *sc, hipStream_t s, int maxit, int per_graph,
+                      int *launches, DevScalars *final_out)
 {
     int slot = 0;
     int n = 0;
@@ -326,7 +424,7 @@ int replay_until_done(pot3d_ctx *c, hipGraphExec_t graph, DevScalars *sc, hipStr
     ++n;
     HIP_TRY(c, hipMemcpyAsync(&c->h_sc[slot], sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIP_TRY(c, hipEventRecord(c->ev_poll[slot], s));
-    const long long max_launches = (long long)maxit / c->graph_m + 3;
+    const long long max_launches = ((long long)maxit + 1) / per_graph + 3;
     for (;;) {
         const int nxt = slot ^ 1;
         HIP_TRY(c, hipGraphLaunch(graph, s));
@@ -350,10 +448,11 @@ void free_ctx(pot3d_ctx *c)
     DeviceGuard guard(c->device);
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
+    if (c->graph_s) (void)hipGraphExecDestroy(c->graph_s);
     for (hipEvent_t *e : {&c->ev_poll[0], &c->ev_poll[1], &c->ev_t0, &c->ev_t1, &c->ev_loop0, &c->ev_loop1})
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
-    void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->p[0], c->p[1],
+    void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
                     c->bplane, c->br, c->partial, c->poles, c->sc,
                     c->r32, c->p32[0], c->p32[1], c->e32, c->sc32};
     for (void *b : bufs)
@@ -425,7 +524,7 @@ int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit)
     return POT3D_OK;
 }
 
-// FP64 Jacobi-PCG: start, then graph replays until done.
+// FP64 Jacobi-PCG: start, then graph replays (one-sweep or two-pass) until done.
 int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters,
              double *relres_true)
 {
@@ -434,10 +533,12 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
     int launches = 0;
     DevScalars fin{};
-    rc = replay_until_done(c, c->graph, c->sc, s, maxit, &launches, &fin);
+    const bool sweep = one_sweep(c);
+    rc = replay_until_done(c, sweep ? c->graph_s : c->graph, c->sc, s, maxit, sweep ? 2 * c->graph_m : c->graph_m,
+                           &launches, &fin);
     if (rc != POT3D_OK) return rc;
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, 64.0, iters, relres_true);
+    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, sweep ? 48.0 : 64.0, iters, relres_true);
 }
 
 // Refinement, outer step: r = b - A x in FP64, then the outer test.  The
@@ -543,7 +644,7 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         rc = refined_start_inner(c, s, tol, maxit - total, out, outer > 0 ? &inner : nullptr, scale_prev);
         if (rc != POT3D_OK) return rc;
         scale_prev = out.scale;
-        rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, &launches, &inner);
+        rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, c->graph_m, &launches, &inner);
         if (rc != POT3D_OK) return rc;
         total += inner.k;
         ++outer;
@@ -727,6 +828,72 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
     return POT3D_OK;
 }
 
+// Average duration of the one-sweep kernel as it runs in a solve: as
+// time_pair, with a graph of `reps` sweeps (sweep, finisher) of a fixed-count
+// FP64 PCG from x = 0 on the context's right-hand side.
+int time_sweeps(pot3d_ctx *ctx, int reps, double *ms_sweep)
+{
+    hipStream_t s = ctx->stream;
+    const int m = std::max(2, reps + (reps & 1));   // even: the buffers alternate across the two replays
+    HIP_TRY(ctx, launch_fill<double>(ctx->x, ctx->npad, 0.0, s));
+    const int rc = start_fp64(ctx, s, 0.0, 1 << 30);
+    if (rc != POT3D_OK) return rc;
+    // per sweep: start, end
+    std::vector<unsigned long long> init(2 * (size_t)m), stamps(2 * (size_t)m);
+    for (int q = 0; q < m; ++q) {
+        init[2 * q] = ~0ull;
+        init[2 * q + 1] = 0ull;
+    }
+    unsigned long long *d_ts = nullptr;
+    HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&d_ts), init.size() * sizeof(unsigned long long)));
+    double *rb[2] = {ctx->r, ctx->r2};
+    double *pb[2] = {ctx->p[0], ctx->p[1]};
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    for (int it = 0; it < m && e == hipSuccess; ++it) {
+        SweepVecs<double> v{};
+        v.r_in = rb[it & 1];
+        v.r_out = rb[(it + 1) & 1];
+        v.p_old = pb[it & 1];
+        v.p_new = pb[(it + 1) & 1];
+        v.x = ctx->x;
+        v.sc = ctx->sc;
+        v.partial = ctx->partial;
+        v.ignore_done = 1;
+        v.tstamp = d_ts + 2 * it;
+        e = launch_sweep<double>(ctx->sweep_rows, ctx->grid_s, v, s);
+        if (e == hipSuccess) e = launch_finish(kFinSweep, ctx->sc, ctx->partial, ctx->grid_s.nblocks, s);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);   // warm-up
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_ts, init.data(), init.size() * sizeof(unsigned long long), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_t0, s);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s);
+    if (e == hipSuccess) e = hipEventRecord(ctx->ev_t1, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(stamps.data(), d_ts, stamps.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    // device ticks -> ms from the replay's span on the device clock and between host events
+    float span_ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&span_ms, ctx->ev_t0, ctx->ev_t1);
+    int khz = 0;
+    (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device);
+    const double span_ticks = (double)(stamps[2 * (size_t)(m - 1) + 1] - stamps[0]);
+    const double ms_per_tick = (span_ticks > 0.0 && span_ms > 0.f) ? span_ms / span_ticks : 1.0 / std::max(1, khz);
+    double t = 0.0;
+    for (int it = 0; it < m && e == hipSuccess; ++it) t += (double)(stamps[2 * it + 1] - stamps[2 * it]) * ms_per_tick;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipFree(d_ts);
+    if (e != hipSuccess) return fail(ctx, POT3D_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
+    *ms_sweep = t / m;
+    return POT3D_OK;
+}
+
 int create_context(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,
                    int upper_bc, int precision, int device, bool serving, pot3d_ctx **out)
 {
@@ -754,6 +921,9 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     c->npad = (long long)nr * nt * c->pitch;
     c->graph_m = std::max(2, env_int("POT3D_GRAPH_ITERS", 16));
     c->graph_m += c->graph_m & 1;   // even, so the p buffers alternate consistently across replays
+    c->iteration = env_int("POT3D_ITERATION", POT3D_ITER_ONE_SWEEP) == POT3D_ITER_TWO_PASS ? POT3D_ITER_TWO_PASS
+                                                                                         : POT3D_ITER_ONE_SWEEP;
+    if (precision != POT3D_FP64) c->iteration = POT3D_ITER_TWO_PASS;
     c->rf.assign(r_faces, r_faces + nr + 1);
     c->tf.assign(t_faces, t_faces + nt + 1);
     c->pf.assign(p_faces, p_faces + np + 1);
@@ -791,7 +961,7 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(dalloc(&c->p[1], (size_t)c->npad));
     CREATE_TRY(dalloc(&c->bplane, (size_t)nt * c->pitch));
     CREATE_TRY(dalloc(&c->br, (size_t)nt * np));
-    CREATE_TRY(dalloc(&c->partial, (size_t)3 * c->max_blocks));
+    CREATE_TRY(dalloc(&c->partial, (size_t)kMaxPartials * c->max_blocks));
     CREATE_TRY(dalloc(&c->poles, (size_t)2 * nr));
     CREATE_TRY(dalloc(&c->sc, 1));
     CREATE_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->h_sc), 2 * sizeof(DevScalars), hipHostMallocDefault));
@@ -803,6 +973,10 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(launch_fill<double>(c->bplane, (long long)nt * c->pitch, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->poles, 2LL * nr, 0.0, c->stream));
     CREATE_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
+    if (sweep_capable(c)) {
+        CREATE_TRY(dalloc(&c->r2, (size_t)c->npad));
+        CREATE_TRY(launch_fill<double>(c->r2, c->npad, 0.0, c->stream));
+    }
     CREATE_TRY(hipStreamSynchronize(c->stream));
     set_tables(c);
     if (precision == POT3D_FP32_REFINED) {
@@ -819,6 +993,7 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     // The iteration graphs are captured once, on the idle context stream
     // (serving slots iterate inside the server's batched graph instead).
     int gc = serving ? POT3D_OK : capture_iterations<double>(c, c->r, c->p[0], c->p[1], c->x, c->sc, &c->graph);
+    if (gc == POT3D_OK && c->r2) gc = capture_sweeps(c, &c->graph_s);
     if (gc == POT3D_OK && precision == POT3D_FP32_REFINED && !serving)
         gc = capture_iterations<float>(c, c->r32, c->p32[0], c->p32[1], c->e32, c->sc32, &c->graph32);
     if (gc != POT3D_OK) {
@@ -832,9 +1007,9 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
 
 size_t context_bytes(const pot3d_ctx *c)
 {
-    size_t b = (size_t)c->npad * sizeof(double) * 4 + (size_t)c->nt * c->pitch * sizeof(double) +
+    size_t b = (size_t)c->npad * sizeof(double) * (c->r2 ? 5 : 4) + (size_t)c->nt * c->pitch * sizeof(double) +
                (size_t)c->nt * c->np * sizeof(double) + c->rows_h.size() * sizeof(RowCoef) +
-               (size_t)3 * c->max_blocks * sizeof(double) + (size_t)2 * c->nr * sizeof(double);
+               (size_t)kMaxPartials * c->max_blocks * sizeof(double) + (size_t)2 * c->nr * sizeof(double);
     if (c->precision == POT3D_FP32_REFINED) b += (size_t)c->npad * sizeof(float) * 4;
     return b;
 }
@@ -970,7 +1145,7 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     out->n = ctx->n;
     out->pitch = ctx->pitch;
     fill_shape(ctx, *out);
-    out->bytes_per_iter = (ctx->precision == POT3D_FP32_REFINED ? 32.0 : 64.0) * (double)ctx->n;
+    out->bytes_per_iter = (ctx->precision == POT3D_FP32_REFINED ? 32.0 : (one_sweep(ctx) ? 48.0 : 64.0)) * (double)ctx->n;
     return POT3D_OK;
 }
 
@@ -981,16 +1156,31 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
     int rc;
-    if (ctx->precision == POT3D_FP32_REFINED)
+    if (ctx->precision == POT3D_FP32_REFINED) {
         rc = time_pair<float>(ctx, ctx->r32, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps, ms_update_p, ms_update_r);
-    else
+    } else if (one_sweep(ctx)) {
+        rc = time_sweeps(ctx, reps, ms_update_p);
+        *ms_update_r = 0.0;
+    } else {
         rc = time_pair<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p, ms_update_r);
+    }
     ctx->have_solution = false;
     if (rc == POT3D_OK) {
         if (const unsigned line = take_oob_line(ctx->stream))
             return fail(ctx, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
     }
     return rc;
+}
+
+int pot3d_set_iteration(pot3d_ctx *ctx, int iteration)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (iteration != POT3D_ITER_TWO_PASS && iteration != POT3D_ITER_ONE_SWEEP)
+        return fail(ctx, POT3D_EINVAL, "iteration must be POT3D_ITER_TWO_PASS or POT3D_ITER_ONE_SWEEP");
+    if (iteration == POT3D_ITER_ONE_SWEEP && !ctx->graph_s)
+        return fail(ctx, POT3D_EINVAL, "the one-sweep iteration is for FP64 contexts with vectors under 4 GiB");
+    ctx->iteration = iteration;
+    return POT3D_OK;
 }
 
 void pot3d_destroy(pot3d_ctx *ctx) { free_ctx(ctx); }

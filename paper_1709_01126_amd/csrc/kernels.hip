@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace pot3d {
 
@@ -779,14 +780,346 @@ stencil_wave_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 }
 
 // ---------------------------------------------------------------------------
+// One-sweep PCG iteration: the Jacobi-PCG of Sec. 2.3 rearranged so that one
+// pass over memory does one iteration (the same iterates in exact arithmetic).
+//
+// Sweep j (j = 0, 1, ...) computes
+//   r_j = r_{j-1} - alpha_{j-1} A p_{j-1}    (r_{j-1} and r_j in two buffers)
+//   x_j = x_{j-1} + alpha_{j-1} p_{j-1}      (in place)
+//   z_j = D^-1 r_j,   p_j = z_j + beta_j p_{j-1}
+//   w_j = A p_j                              (not stored)
+// and per-workgroup partial sums of r_j.z_j, r_j.r_j, p_j.w_j, z_j.w_j and
+// w_j.D^-1 w_j.  The finisher then has alpha_j = r_j.z_j / p_j.w_j, and as
+// r_{j+1} = r_j - alpha_j w_j,
+//   r_{j+1}.z_{j+1} = r_j.z_j - 2 alpha_j z_j.w_j + alpha_j^2 w_j.D^-1 w_j,
+// which gives beta_{j+1} before r_{j+1} exists.  Sweep 0 runs with
+// alpha = beta = 0 and p_{-1} = 0.  Traffic: 48 bytes per unknown per
+// iteration (read r, p_old, x; write r, p, x) against 64 for the two passes,
+// and one stencil launch and one finisher instead of two of each.
+//
+// p_j feeds A p_j on a one-cell ring around each cell, and A p_{j-1} is
+// needed on that ring too, so p_{j-1} is read with a two-cell ring.  A
+// workgroup owns tj x tk interior (theta, phi) cells over a chunk of radial
+// layers and holds them with the ring as a box of 4R rows x 64 lanes
+// (tj <= 4R - 4, tk <= 60).  Box row e is polar row j0 - 2 + e; lane c is
+// azimuthal cell (k0 - 2 + c) mod np, so periodic phi needs no special case
+// and phi neighbours are the neighbouring lanes (DPP shifts).  Wavefront w
+// holds box rows [wR, wR + R).  For each layer a of the chunk, and one layer
+// beyond each end:
+//   stage A, layer a, on the box less its outer ring: A p_{j-1}, r_j, z_j,
+//     p_j (theta neighbours of p_{j-1} from an LDS plane, radial ones from
+//     registers);
+//   stage B, layer a - 1, interior: w_j = A p_j and the dot products (theta
+//     neighbours of p_j from a second LDS plane).
+// Each plane has three LDS slots in rotation: one barrier per layer.
+// ---------------------------------------------------------------------------
+// Reciprocal of a positive normal value: the hardware estimate refined by
+// two Newton steps y <- y + y (1 - d y), each of which squares the relative
+// error (within about an ulp of 1/d).
+__device__ __forceinline__ double recip(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-d, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float d) { return 1.0f / d; }
+
+// Lane l receives lane l-1 (shr) or l+1 (shl); the lane past the wavefront's
+// end receives 0 (DPP bound control: no initialised destination needed).
+__device__ __forceinline__ double shr1(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double shl1(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float shl1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+
+// Element at a 32-bit byte offset from a vector's base: the access takes the
+// base in scalar registers and a 32-bit offset per lane.  (The one-sweep
+// path is used for vectors under 4 GiB.)
+template <typename T>
+__device__ __forceinline__ GPtr<T> at_byte(GPtr<T> base, unsigned boff)
+{
+    using C = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return (GPtr<T>)((__attribute__((address_space(1))) C *)base + boff);
+}
+#ifdef POT3D_CHECKED
+#define SWEEP_AT(base, boff) ((base) + CHK((boff) / sizeof(V), g.npad))
+#else
+#define SWEEP_AT(base, boff) at_byte((base), (boff))
+#endif
+
+template <int R, typename V>
+__device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V> &v, const RowCoef *__restrict__ rows,
+                                           const V *__restrict__ rin, V *__restrict__ rout, const V *__restrict__ pold,
+                                           V *__restrict__ pnew, V *__restrict__ xvec, const int b)
+{
+    constexpr int ER = kWaves * R;
+    __shared__ V lp[3][ER][kWave];   // p_{j-1} of three layers
+    __shared__ V lq[3][ER][kWave];   // p_j of three layers
+    __shared__ double lc[3][ER][8];  // row coefficients of three layers
+    __shared__ double red[kWaves][5];
+    static_assert(ER * 8 <= kThreads, "coefficient staging");
+
+    const CPtr<const DevScalars> csc = to_const(v.sc);
+    if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
+    if (v.tstamp && threadIdx.x == 0) atomicMin(&v.tstamp[0], wall_clock64());
+
+    const GPtr<const V> grin = to_global(rin), gpold = to_global(pold);
+    const GPtr<V> grout = to_global(rout), gpnew = to_global(pnew), gx = to_global(xvec);
+    const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih);
+    const GPtr<double> gpart = to_global(v.partial);
+
+    // Workgroup -> tile, XCD-aware as in march_body.
+    const int per = g.nblocks / kXcds;
+    int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
+    if (g.reverse) L = g.nblocks - 1 - L;
+    const int kt = L % g.ntk;
+    L /= g.ntk;
+    const int ic = L % g.nchunk;
+    const int jt = L / g.nchunk;
+    const int nt = g.nt, np = g.np, nr = g.nr;
+    const int i0 = ic * g.ci;
+    const int i1 = min(i0 + g.ci, nr);
+    const int j0 = jt * g.tj;
+    const int k0 = kt * g.tk;
+    const int tjn = min(g.tj, nt - j0);   // interior rows of this tile
+    const int tkn = min(g.tk, np - k0);   // interior cells of a row
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    // This lane's azimuthal cell; lanes past the box's right ring repeat its
+    // last cell (their values are never used).
+    int kk = (k0 - 2 + min(lane, tkn + 3)) % np;
+    if (kk < 0) kk += np;
+    const unsigned kboff = (unsigned)kk * (unsigned)sizeof(V);
+    (void)kboff;
+    const bool col_in = lane >= 2 && lane < tkn + 2;    // interior cell
+    const bool col_a = lane >= 1 && lane < tkn + 3;     // stage-A cell
+    const V dph = (V)gdphi[CHK(kk, np)];
+    const V ihm = (V)gih[CHK(kk == 0 ? np - 1 : kk - 1, np)];
+    const V ihk = (V)gih[CHK(kk, np)];
+    const V ihs = ihm + ihk;   // the phi part of the diagonal, / pq
+    const V alpha = (V)csc->alpha, beta = (V)csc->beta;
+
+    // Per lane: the byte offset of the cell within a layer for each of this
+    // wavefront's box rows (rows outside the grid read the nearest grid row),
+    // and whether the row is interior.  Values read outside the grid, or
+    // computed from such values, only ever meet zero weights: the pole rows
+    // have no theta coupling across the pole and the radial boundary rows none
+    // outside the shell, so they need no masking.
+    const int e0 = w * R;
+    unsigned vrow[R];
+    bool oki[R];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int e = e0 + m;
+        vrow[m] = (unsigned)(min(max(j0 - 2 + e, 0), nt - 1) * g.pitch + kk) * (unsigned)sizeof(V);
+        oki[m] = e >= 2 && e < tjn + 2;
+    }
+    const unsigned planeb = (unsigned)g.plane * (unsigned)sizeof(V);
+    auto layer_b = [&](int a) { return (unsigned)min(max(a, 0), nr - 1) * planeb; };
+    auto slot = [](int a) { return (a + 3) % 3; };
+    auto load_p = [&](int a, V (&dst)[R]) {
+        const unsigned lb = layer_b(a);
+#pragma unroll
+        for (int m = 0; m < R; ++m) dst[m] = *SWEEP_AT(gpold, lb + vrow[m]);
+    };
+    // r_{j-1} of layer a; x_{j-1} on the interior of the chunk's own layers
+    auto load_rx = [&](int a, V (&rdst)[R], V (&xdst)[R]) {
+        const bool own = a >= i0 && a < i1;
+        const unsigned lb = layer_b(a);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            rdst[m] = V(0);   // the box's outer ring needs no r
+            if (e0 + m >= 1 && e0 + m < tjn + 3) rdst[m] = *SWEEP_AT(grin, lb + vrow[m]);
+            xdst[m] = V(0);
+            if (own && oki[m] && col_in) xdst[m] = stream_load(SWEEP_AT(gx, lb + vrow[m]));
+        }
+    };
+    // Row coefficients of the box rows of one layer, staged in LDS (three
+    // layers in rotation) and read back as broadcasts: rm rp tm tp s pq.
+    auto stage_coef = [&](int a) {
+        const int t = threadIdx.x;
+        if (t < ER * 8) {
+            const int e = t >> 3, f = t & 7;
+            const int jc = min(max(j0 - 2 + e, 0), nt - 1);
+            const int ac = min(max(a, 0), nr - 1);
+            const GPtr<const double> src = to_global(reinterpret_cast<const double *>(rows));
+            lc[slot(a)][e][f] = src[CHK(((long long)ac * nt + jc) * 8 + f, 8LL * nr * nt)];
+        }
+    };
+    auto coef = [&](int sl, int e) -> RowCoef {
+        RowCoef r;
+        r.rm = lc[sl][e][0];
+        r.rp = lc[sl][e][1];
+        r.tm = lc[sl][e][2];
+        r.tp = lc[sl][e][3];
+        r.s = lc[sl][e][4];
+        r.pq = lc[sl][e][5];
+        r.pad0 = r.pad1 = 0.0;
+        return r;
+    };
+    // 7-point operator at one cell from the centre, radial and theta
+    // neighbours; the phi neighbours come from the adjacent lanes.
+    auto apply = [&](const RowCoef &rc, V pc, V pim, V pip, V pjm, V pjp) -> V {
+        const V pkm = shr1(pc), pkp = shl1(pc);
+        V t = (V)rc.s * pc;
+        t = vfma<V>(-(V)rc.rm, pim, t);
+        t = vfma<V>(-(V)rc.rp, pip, t);
+        t = vfma<V>(-(V)rc.tm, pjm, t);
+        t = vfma<V>(-(V)rc.tp, pjp, t);
+        V u = ihm * (pc - pkm);
+        u = vfma<V>(ihk, pc - pkp, u);
+        return vfma<V>(dph, t, (V)rc.pq * u);
+    };
+
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
+    // One layer step: stage A at layer a, stage B at layer a - 1.  rv, xo:
+    // r_{j-1}, x_{j-1} of layer a (loaded one step ahead; the next layer's go
+    // to rv_n, xo_n).  z1, i1: z_j and 1/diag of layer a - 1 (stage B); this
+    // step's go to za, ia.  Each wavefront reads its own rows of the LDS
+    // planes at any time (it alone writes them) and other rows only across a
+    // barrier.
+    auto step = [&](int a, V (&rv)[R], V (&xo)[R], V (&rv_n)[R], V (&xo_n)[R], V (&z1)[R], V (&i1_)[R], V (&za)[R],
+                    V (&ia)[R]) {
+        const bool own = a >= i0 && a < i1;
+        const unsigned lb = layer_b(a);
+        const int sa = slot(a), sa1 = slot(a + 1), sb = slot(a - 1), sb2 = slot(a - 2);
+        V pn[R];
+        load_p(a + 2, pn);
+        load_rx(a + 1, rv_n, xo_n);
+        stage_coef(a + 1);
+        V qa[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int e = e0 + m;
+            const RowCoef rc = coef(sa, e);
+            const V pc = lp[sa][e][lane];
+            const V ap = apply(rc, pc, lp[sb][e][lane], lp[sa1][e][lane], lp[sa][max(e - 1, 0)][lane],
+                               lp[sa][min(e + 1, ER - 1)][lane]);
+            const V rn = vfma<V>(-alpha, ap, rv[m]);
+            const V inv = recip(vfma<V>(dph, (V)rc.s, (V)rc.pq * ihs));
+            const V zn = rn * inv;
+            const V qn = vfma<V>(beta, pc, zn);
+            qa[m] = qn;
+            za[m] = zn;
+            ia[m] = inv;
+            lq[sa][e][lane] = qn;
+            if (own && oki[m] && col_in) {
+                stream_store(SWEEP_AT(grout, lb + vrow[m]), rn);
+                stream_store(SWEEP_AT(gpnew, lb + vrow[m]), qn);
+                stream_store(SWEEP_AT(gx, lb + vrow[m]), vfma<V>(alpha, pc, xo[m]));
+                acc0 = __builtin_fma((double)rn, (double)zn, acc0);
+                acc1 = __builtin_fma((double)rn, (double)rn, acc1);
+            }
+        }
+        if (a - 1 >= i0) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                if (!oki[m]) continue;   // uniform
+                const int e = e0 + m;
+                const RowCoef rc = coef(sb, e);
+                const V qc = lq[sb][e][lane];
+                const V wv = apply(rc, qc, lq[sb2][e][lane], qa[m], lq[sb][e - 1][lane], lq[sb][e + 1][lane]);
+                if (col_in) {
+                    acc2 = __builtin_fma((double)qc, (double)wv, acc2);
+                    acc3 = __builtin_fma((double)z1[m], (double)wv, acc3);
+                    acc4 = __builtin_fma((double)wv * (double)i1_[m], (double)wv, acc4);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < R; ++m) lp[slot(a + 2)][e0 + m][lane] = pn[m];
+        __syncthreads();
+    };
+
+    V rvA[R], xoA[R], rvB[R], xoB[R], zA[R], iA[R], zB[R], iB[R];
+    stage_coef(i0 - 1);
+    load_rx(i0 - 1, rvA, xoA);
+    {
+        V t0[R], t1[R], t2[R];
+        load_p(i0 - 2, t0);
+        load_p(i0 - 1, t1);
+        load_p(i0, t2);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            lp[slot(i0 - 2)][e0 + m][lane] = t0[m];
+            lp[slot(i0 - 1)][e0 + m][lane] = t1[m];
+            lp[slot(i0)][e0 + m][lane] = t2[m];
+            zA[m] = iA[m] = V(0);
+        }
+    }
+    __syncthreads();
+    int a = i0 - 1;
+    for (; a + 1 <= i1; a += 2) {
+        step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB);
+        step(a + 1, rvB, xoB, rvA, xoA, zB, iB, zA, iA);
+    }
+    if (a <= i1) step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB);
+
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        acc0 += __shfl_xor(acc0, off, kWave);
+        acc1 += __shfl_xor(acc1, off, kWave);
+        acc2 += __shfl_xor(acc2, off, kWave);
+        acc3 += __shfl_xor(acc3, off, kWave);
+        acc4 += __shfl_xor(acc4, off, kWave);
+    }
+    if (lane == 0) {
+        red[w][0] = acc0;
+        red[w][1] = acc1;
+        red[w][2] = acc2;
+        red[w][3] = acc3;
+        red[w][4] = acc4;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = threadIdx.x;
+        double s = 0.0;
+#pragma unroll
+        for (int u = 0; u < kWaves; ++u) s += red[u][q];
+        gpart[CHK((long long)q * g.nblocks + b, 5LL * g.nblocks)] = s;
+    }
+    if (v.tstamp) {   // timing runs: this workgroup's end
+        __syncthreads();
+        if (threadIdx.x == 0) atomicMax(&v.tstamp[1], wall_clock64());
+    }
+}
+#undef SWEEP_AT
+
+template <int R, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_sweep(GridArgs g, SweepVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ rin,
+              V *__restrict__ rout, const V *__restrict__ pold, V *__restrict__ pnew, V *__restrict__ x)
+{
+    sweep_body<R, V>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
 // Finishers: one workgroup sums the per-workgroup partials in a fixed order
 // and advances the scalar state of the iteration.
 // ---------------------------------------------------------------------------
 constexpr int kFinThreads = 256;
 
-__device__ __forceinline__ void block_sums(const double *partial, int nb, int ncomp, double out[3])
+__device__ __forceinline__ void block_sums(const double *partial, int nb, int ncomp, double out[kMaxPartials])
 {
-    __shared__ double sh[3][kFinThreads];
+    __shared__ double sh[kMaxPartials][kFinThreads];
     const int t = threadIdx.x;
     for (int c = 0; c < ncomp; ++c) {
         double s = 0.0;
@@ -808,8 +1141,10 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
     const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner ||
                         which == kFinResume;
     if (!always && sc->done) return;
-    double s[3] = {0.0, 0.0, 0.0};
-    const int ncomp = (which == kFinSigma) ? 1 : ((which == kFinInit || which == kFinOuter) ? 3 : 2);
+    double s[kMaxPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    const int ncomp = (which == kFinSigma) ? 1
+                      : (which == kFinSweep) ? 5
+                      : ((which == kFinInit || which == kFinOuter) ? 3 : 2);
     block_sums(partial, nb, ncomp, s);
     if (threadIdx.x != 0) return;
     if (which == kFinInit) {
@@ -822,6 +1157,7 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
         sc->alpha = 0.0;
         sc->beta = 0.0;
         sc->k = 0;
+        sc->sweep = 0;
         sc->zero_solution = 0;
         sc->done = 0;
         sc->status = POT3D_ENOCONV;
@@ -879,6 +1215,47 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
                 sc->done = 1;
             }
         }
+    } else if (which == kFinSweep) {
+        // After sweep j of the one-sweep iteration (partials: r_j.z_j, r_j.r_j,
+        // p_j.w_j, z_j.w_j, w_j.D^-1 w_j).  For j > 0, r_j is the residual of
+        // iteration j: convergence test.  Then alpha_j, and beta_{j+1} from the
+        // predicted r_{j+1}.z_{j+1}; a prediction that rounding made
+        // non-positive restarts the recurrence (beta = 0, a steepest-descent
+        // step, which the next sweep's true r.z then corrects).
+        const int j = sc->sweep;
+        sc->sweep = j + 1;
+        bool stop = false;
+        if (j > 0) {
+            sc->k = j;
+            sc->rr = s[1];
+            const double rel = sqrt(s[1]) / sc->bnorm;
+            sc->relres = rel;
+            if (!isfinite(rel)) {
+                sc->status = POT3D_EBREAKDOWN;
+                stop = true;
+            } else if (rel <= sc->tol) {
+                sc->status = POT3D_OK;
+                stop = true;
+            } else if (j >= sc->maxit) {
+                sc->status = POT3D_ENOCONV;
+                stop = true;
+            }
+        }
+        if (!stop) {
+            const double rho = s[0], sigma = s[2];
+            sc->rho = rho;
+            sc->sigma = sigma;
+            if (!(sigma > 0.0) || !isfinite(sigma)) {
+                sc->status = POT3D_EBREAKDOWN;
+                stop = true;
+            } else {
+                const double alpha = rho / sigma;
+                const double rho_next = fma(alpha * alpha, s[4], fma(-2.0 * alpha, s[3], rho));
+                sc->alpha = alpha;
+                sc->beta = (rho_next > 0.0 && isfinite(rho_next)) ? rho_next / rho : 0.0;
+            }
+        }
+        if (stop) sc->done = 1;
     } else if (which == kFinTrue) {  // ||b - A x|| / ||b|| from a residual pass with store_r = 0
         sc->relres_true = (sc->bnorm > 0.0) ? sqrt(s[1]) / sc->bnorm : 0.0;
     } else if (which == kFinOuter) {
@@ -1189,6 +1566,33 @@ template hipError_t launch_stencil<double>(int, int, const GridArgs &, const Ste
                                           hipEvent_t, hipEvent_t);
 template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t,
                                          hipEvent_t, hipEvent_t);
+
+template <typename V>
+hipError_t launch_sweep(int rows, const GridArgs &g, const SweepVecs<V> &v, hipStream_t s)
+{
+    const dim3 grid(g.nblocks), block(kThreads);
+    switch (rows) {
+    case 4: stencil_sweep<4, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
+    case 6: stencil_sweep<6, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
+    case 8: stencil_sweep<8, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_sweep<double>(int, const GridArgs &, const SweepVecs<double> &, hipStream_t);
+
+template <typename V>
+int sweep_blocks_per_cu(int rows)
+{
+    const void *f = rows == 4   ? reinterpret_cast<const void *>(&stencil_sweep<4, V>)
+                    : rows == 6 ? reinterpret_cast<const void *>(&stencil_sweep<6, V>)
+                    : rows == 8 ? reinterpret_cast<const void *>(&stencil_sweep<8, V>)
+                                : nullptr;
+    int n = 0;
+    if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) return 0;
+    return n;
+}
+template int sweep_blocks_per_cu<double>(int);
 
 template <int TJ, typename V>
 hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)

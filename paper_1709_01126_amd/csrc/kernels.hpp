@@ -13,8 +13,13 @@ enum FinWhich : int {
     kFinTrue = 3,   // after a residual pass without store: true relative residual
     kFinOuter = 4,  // refinement, after the FP64 residual pass: outer test, scale = 1/||r||
     kFinInner = 5,  // refinement, after the r.z pass on the FP32 residual: inner start
-    kFinResume = 6  // refinement, reliable update: as kFinInner, keeping the direction
+    kFinResume = 6, // refinement, reliable update: as kFinInner, keeping the direction
+    kFinSweep = 7   // one-sweep iteration: convergence test, alpha, predicted r.z, beta
 };
+
+// Partial sums per workgroup that a finisher may read (the one-sweep kernel
+// writes five).
+constexpr int kMaxPartials = 5;
 
 // Stencil kernel shapes.  march: TJ x 64 tile per workgroup with an LDS plane;
 // wave: M rows x 128 cells per wavefront, registers and lane shuffles only.
@@ -34,6 +39,13 @@ hipError_t launch_stencil(int mode, int tile, const GridArgs &g, const StencilVe
 // Workgroups of a stencil kernel that fit on one compute unit at once (0 if unknown).
 template <typename V>
 int stencil_blocks_per_cu(int mode, int tile);
+
+// One-sweep iteration kernel, `rows` rows of the tile box per wavefront (4, 6 or 8).
+template <typename V>
+hipError_t launch_sweep(int rows, const GridArgs &g, const SweepVecs<V> &v, hipStream_t s);
+template <typename V>
+int sweep_blocks_per_cu(int rows);
+inline bool valid_sweep_rows(int rows) { return rows == 4 || rows == 6 || rows == 8; }
 
 // Checked builds: the source line of the first out-of-range index seen since
 // the last call (0 if none), after waiting for stream s.  Normal builds: 0.

@@ -44,7 +44,8 @@ struct alignas(64) DevScalars {
     int done;          // 1: all further iteration kernels are no-ops
     int status;        // POT3D_* status once done
     int zero_solution; // ||b|| = 0: the answer is Phi = 0
-    int pad[3];
+    int sweep;         // one-sweep iteration: sweeps done since the start
+    int pad[2];
     double scale;      // refinement: 1 / ||r64|| used to normalise the FP32 residual
 };
 
@@ -57,6 +58,7 @@ struct GridArgs {
     int nblocks;
     int reverse;          // 1: walk the tiles in reverse order
     long long npad;       // elements of each vector (nr * nt * pitch), for checked builds
+    int tj, tk;           // one-sweep kernel: interior rows and cells of a tile
     const RowCoef *rows;  // nr * nt
     const double *dphi;   // np: phi_f[k+1] - phi_f[k]
     const double *ih;     // np: 1 / (phi_{k+1} - phi_k), wrapping at k = np-1
@@ -84,6 +86,22 @@ struct StencilVecs {
     int ignore_done;  // 1: run even when sc->done is set
     unsigned long long *tstamp;   // timing runs only: [0] earliest workgroup start, [1] latest
                                   // workgroup end (device wall clock); NULL otherwise
+};
+
+// Vectors of one sweep of the one-sweep iteration (sweep j: r_j from r_{j-1}
+// and A p_{j-1}, x_j, p_j; see fused_body).  r and p alternate between two
+// buffers; x is updated in place.
+template <typename V>
+struct SweepVecs {
+    const V *r_in;    // r_{j-1}
+    V *r_out;         // r_j
+    const V *p_old;   // p_{j-1}
+    V *p_new;         // p_j
+    V *x;             // x_{j-1} in, x_j out
+    const DevScalars *sc;   // alpha_{j-1}, beta_j
+    double *partial;  // [5][nblocks]: r.z, r.r, p.Ap, z.Ap, Ap.D^-1 Ap
+    int ignore_done;  // 1: run even when sc->done is set
+    unsigned long long *tstamp;   // timing runs only, as in StencilVecs
 };
 
 // One slot of a batched stencil launch (device-resident table).  `out` is the

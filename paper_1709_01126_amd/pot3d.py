@@ -20,12 +20,13 @@ OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EBREAKDOWN = 0, -1, -2, -3, -4, -5
 UPPER_SOURCE_SURFACE, UPPER_CLOSED_WALL = 0, 1
 FP64, FP32_REFINED = 0, 1
 REFINE_RESTART, REFINE_RELIABLE = 0, 1
+ITER_TWO_PASS, ITER_ONE_SWEEP = 0, 1
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
                 EBREAKDOWN: "EBREAKDOWN"}
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
             "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
-            "pot3d_set_refinement_mode", "pot3d_destroy",
+            "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
             "pot3d_server_set_cache_budget", "pot3d_server_get_stats", "pot3d_server_destroy",
@@ -38,7 +39,8 @@ class pot3d_stats(ctypes.Structure):
                 ("solve_ms", ctypes.c_double), ("loop_ms", ctypes.c_double), ("bytes_per_iter", ctypes.c_double),
                 ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_p", ctypes.c_int),
                 ("tile_r", ctypes.c_int), ("chunk_p", ctypes.c_int), ("chunk_r", ctypes.c_int),
-                ("blocks_p", ctypes.c_int), ("blocks_r", ctypes.c_int)]
+                ("blocks_p", ctypes.c_int), ("blocks_r", ctypes.c_int), ("iteration", ctypes.c_int),
+                ("sweep_rows", ctypes.c_int), ("chunk_s", ctypes.c_int), ("blocks_s", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -105,6 +107,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_set_refinement.restype = i
     lib.pot3d_set_refinement_mode.argtypes = [vp, i]
     lib.pot3d_set_refinement_mode.restype = i
+    lib.pot3d_set_iteration.argtypes = [vp, i]
+    lib.pot3d_set_iteration.restype = i
     lib.pot3d_destroy.argtypes = [vp]
     lib.pot3d_destroy.restype = None
     lib.pot3d_last_error.argtypes = [vp]
@@ -222,6 +226,10 @@ def pot3d_set_refinement_mode(ctx, mode):
     return load().pot3d_set_refinement_mode(ctx, int(mode))
 
 
+def pot3d_set_iteration(ctx, iteration):
+    return load().pot3d_set_iteration(ctx, int(iteration))
+
+
 def pot3d_destroy(ctx):
     if ctx:
         load().pot3d_destroy(ctx)
@@ -230,12 +238,15 @@ def pot3d_destroy(ctx):
 class Solver:
     """Owns one context; raises Pot3dError on EINVAL/ENOMEM/EDEVICE."""
 
-    def __init__(self, r_faces, t_faces, p_faces, upper_bc=UPPER_SOURCE_SURFACE, precision=FP64, device=0):
+    def __init__(self, r_faces, t_faces, p_faces, upper_bc=UPPER_SOURCE_SURFACE, precision=FP64, device=0,
+                 iteration=None):
         st, ctx = pot3d_create(r_faces, t_faces, p_faces, upper_bc, precision, device)
         if st != OK:
             raise Pot3dError(st, pot3d_last_error(None))
         self.ctx = ctx
         self.nr, self.nt, self.np = len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1
+        if iteration is not None:
+            self.set_iteration(iteration)
 
     @property
     def shape(self):
@@ -300,6 +311,9 @@ class Solver:
 
     def set_refinement_mode(self, mode):
         self._check(pot3d_set_refinement_mode(self.ctx, mode), (OK,))
+
+    def set_iteration(self, iteration):
+        self._check(pot3d_set_iteration(self.ctx, iteration), (OK,))
 
     def close(self):
         if self.ctx:

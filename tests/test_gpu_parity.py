@@ -72,6 +72,10 @@ def label(case):
     return "x".join(str(v) for v in case[:3]) + "-" + "-".join(case[3:])
 
 
+# the two forms of the FP64 iteration (one sweep is the default)
+ITERATIONS = pytest.mark.parametrize("iteration", [P.ITER_ONE_SWEEP, P.ITER_TWO_PASS], ids=["one_sweep", "two_pass"])
+
+
 @pytest.fixture(scope="module", autouse=True)
 def announce():
     print(f"\n[gpu parity] library {P.pot3d_version()}", flush=True)
@@ -137,16 +141,20 @@ def iters_close(a, b):
     return abs(a - b) <= max(2, int(0.005 * max(a, b)))
 
 
+@ITERATIONS
 @pytest.mark.parametrize("case", GRIDS, ids=label)
-def test_solve_matches_oracle(case):
+def test_solve_matches_oracle(case, iteration):
     rf, tf, pf = make_faces(*case)
     br, _ = magnetograms.br_harmonics(tf, pf, 6, seed=7)
     tol = 1e-10
     ref = oracle.solve(rf, tf, pf, br, tol, 100_000)
-    with P.Solver(rf, tf, pf) as s:
+    with P.Solver(rf, tf, pf, iteration=iteration) as s:
         phi, st, it, rr = gpu_solve(s, br, tol, 100_000)
         stats = s.stats()
-    print(f"[solve] {label(case)} iters gpu={it} oracle={ref['iters']} true_relres={rr:.2e}", flush=True)
+    print(f"[solve] {label(case)} iteration={iteration} iters gpu={it} oracle={ref['iters']} "
+          f"true_relres={rr:.2e}", flush=True)
+    assert stats["iteration"] == iteration
+    assert stats["bytes_per_iter"] == (48.0 if iteration == P.ITER_ONE_SWEEP else 64.0) * stats["n"]
     assert st == P.OK and ref["status"] == oracle.OK
     assert iters_close(it, ref["iters"]), (it, ref["iters"])
     check_solution(phi, ref["phi"])
@@ -157,15 +165,16 @@ def test_solve_matches_oracle(case):
     assert rr <= 1e-8
 
 
+@ITERATIONS
 @pytest.mark.parametrize("case", [GRIDS[4], GRIDS[6]], ids=label)
-def test_fixed_iteration_count_parity(case):
+def test_fixed_iteration_count_parity(case, iteration):
     rf, tf, pf = make_faces(*case)
     br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
-    for K in (1, 17, 50):
+    for K in (1, 2, 17, 50):
         xo, io, _, so = oracle.pcg(coef, b, 0.0, K)
-        with P.Solver(rf, tf, pf) as s:
+        with P.Solver(rf, tf, pf, iteration=iteration) as s:
             phi, st, it, _ = gpu_solve(s, br, 0.0, K)
         assert st == P.ENOCONV and so == oracle.ENOCONV and it == io == K
         check_solution(phi, xo, tol=1e-11)
@@ -188,20 +197,22 @@ def test_small_workload_parity_and_poles():
     np.testing.assert_allclose(south, so, rtol=1e-8, atol=1e-8 * np.abs(so).max())
 
 
-def test_deterministic_repeat():
+@ITERATIONS
+def test_deterministic_repeat(iteration):
     rf, tf, pf = make_faces(*GRIDS[4])
     br = magnetograms.br_bipoles(tf, pf, 30, seed=5)
-    with P.Solver(rf, tf, pf) as s:
+    with P.Solver(rf, tf, pf, iteration=iteration) as s:
         a = gpu_solve(s, br, 1e-10, 100_000)
         b = gpu_solve(s, br, 1e-10, 100_000)
     assert a[2] == b[2] and np.array_equal(a[0], b[0])
 
 
-def test_edge_cases():
+@ITERATIONS
+def test_edge_cases(iteration):
     rf, tf, pf = make_faces(*GRIDS[4])
     nr, nt, np_ = GRIDS[4][:3]
     br = magnetograms.br_bipoles(tf, pf, 30, seed=5)
-    with P.Solver(rf, tf, pf) as s:
+    with P.Solver(rf, tf, pf, iteration=iteration) as s:
         # zero data: Phi = 0 exactly, no iterations, even from a nonzero start
         phi, st, it, rr = gpu_solve(s, np.zeros((nt, np_)), 1e-10, 100, phi0=np.ones((nr, nt, np_)))
         assert st == P.OK and it == 0 and np.all(phi == 0)
@@ -234,7 +245,12 @@ def test_edge_cases():
                                  {"POT3D_TILE": "102"}, {"POT3D_TILE": "104"}, {"POT3D_TILE": "108"},
                                  {"POT3D_CI": "1"}, {"POT3D_CI": "1000"}, {"POT3D_PITCH_ALIGN": "1"},
                                  {"POT3D_PITCH_ALIGN": "32", "POT3D_GRAPH_ITERS": "2"},
-                                 {"POT3D_TILE": "16", "POT3D_CI": "3"}])
+                                 {"POT3D_TILE": "16", "POT3D_CI": "3"},
+                                 {"POT3D_ITERATION": "0"},
+                                 {"POT3D_SWEEP_ROWS": "6"}, {"POT3D_SWEEP_ROWS": "8"},
+                                 {"POT3D_SWEEP_TK": "1"}, {"POT3D_SWEEP_TK": "16"}, {"POT3D_SWEEP_TK": "60"},
+                                 {"POT3D_SWEEP_CI": "1"}, {"POT3D_SWEEP_CI": "1000"},
+                                 {"POT3D_REVERSE_S": "1", "POT3D_TARGET_BLOCKS_S": "7"}])
 def test_launch_shapes_agree(env, monkeypatch):
     for k, v in env.items():
         monkeypatch.setenv(k, v)

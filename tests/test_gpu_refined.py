@@ -154,5 +154,8 @@ def test_refinement_modes(case):
     with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
         with pytest.raises(P.Pot3dError):
             s.set_refinement_mode(7)
+        # the FP32 inner iteration has the two-pass form only
+        assert P.pot3d_set_iteration(s.ctx, P.ITER_ONE_SWEEP) == P.EINVAL
+        assert P.pot3d_set_iteration(s.ctx, P.ITER_TWO_PASS) == P.OK
     with P.Solver(rf, tf, pf) as s64:
         assert P.pot3d_set_refinement_mode(s64.ctx, P.REFINE_RELIABLE) == P.EINVAL
