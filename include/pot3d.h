@@ -75,8 +75,8 @@ enum pot3d_iteration {
     POT3D_ITER_ONE_SWEEP = 1   /* one sweep per iteration: the r/x update of iteration j-1
                                   and the direction update of iteration j together, with
                                   r.z of the next residual predicted from p.Ap, z.Ap and
-                                  Ap.D^-1 Ap (48 bytes per unknown).  The same PCG in exact
-                                  arithmetic.  Default for FP64 contexts.                   */
+                                  Ap.D^-1 Ap (48 bytes per unknown in FP64, 24 in FP32).  The
+                                  same PCG in exact arithmetic.  Default.                   */
 };
 
 enum pot3d_precision {
@@ -96,7 +96,8 @@ typedef struct pot3d_stats {
     double solve_ms;         /* wall time of the last solve call on the device             */
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 48 N (FP64, one
-                                sweep), 64 N (FP64, two passes), 32 N (FP32 inner)         */
+                                sweep), 64 N (FP64, two passes), 24 N / 32 N (FP32 inner,
+                                one sweep / two passes)                                    */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -104,7 +105,7 @@ typedef struct pot3d_stats {
                                 cells; 102/104/108 = wavefront tile of 2/4/8 rows x 128   */
     int chunk_p, chunk_r;    /* radial layers per workgroup chunk, per pass                 */
     int blocks_p, blocks_r;  /* workgroups per launch, per pass                              */
-    int iteration;           /* POT3D_ITER_* of the last solve (two-pass in refined mode)   */
+    int iteration;           /* POT3D_ITER_* of the iterations (FP32 inner ones if refined) */
     int sweep_rows;          /* one-sweep kernel: tile box rows per wavefront (4, 6 or 8)   */
     int chunk_s, blocks_s;   /* one-sweep kernel: radial layers per chunk, workgroups      */
 } pot3d_stats;
@@ -117,7 +118,7 @@ typedef struct pot3d_stats {
  *   nr >= 2, nt >= 2, np >= 3.  Arrays are host memory, copied.
  *   upper_bc   POT3D_UPPER_SOURCE_SURFACE (closed wall is rejected with POT3D_EINVAL)
  *   precision  POT3D_FP64 or POT3D_FP32_REFINED
- * On success *out owns device buffers of about 40 N bytes (FP64) or 32 N + 16 N
+ * On success *out owns device buffers of about 40 N bytes (FP64) or 32 N + 20 N
  * bytes (FP32-refined).
  */
 int pot3d_create(const double *r_faces, int nr,
@@ -185,8 +186,7 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
  * start and its last workgroup's end on the device wall clock.
  * Two-pass iteration: *ms_update_p = the p update (A p, p.Ap), *ms_update_r =
  * the r/x update (r.z, r.r).  One-sweep iteration: *ms_update_p = the sweep,
- * *ms_update_r = 0.  FP32-refined contexts time the FP32 inner kernels (two
- * passes).  It runs on the vectors the context holds and overwrites them; a
+ * *ms_update_r = 0.  FP32-refined contexts time the FP32 inner kernels.  It runs on the vectors the context holds and overwrites them; a
  * later solve re-initializes everything.
  */
 int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
@@ -217,10 +217,12 @@ int pot3d_set_refinement(pot3d_ctx *ctx, double inner_tol, int max_outer);
 int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
 
 /*
- * FP64 contexts: the form of the PCG iteration (POT3D_ITER_ONE_SWEEP, the
- * default, or POT3D_ITER_TWO_PASS; the environment variable POT3D_ITERATION
- * = 0 or 1 sets the default of new contexts).  Both run the Jacobi-PCG of
- * Sec. 2.3; their iterates agree to rounding.  FP32-refined contexts accept
+ * The form of the PCG iteration: of the FP64 iterations, or in FP32-refined
+ * contexts of the FP32 inner iterations (POT3D_ITER_ONE_SWEEP, the default,
+ * or POT3D_ITER_TWO_PASS; the environment variable POT3D_ITERATION = 0 or 1
+ * sets the default of new contexts).  Both run the Jacobi-PCG of Sec. 2.3;
+ * their iterates agree to rounding.  The one-sweep form needs vectors under
+ * 4 GiB (FP64: N < 2^29 with the row padding); larger contexts accept
  * POT3D_ITER_TWO_PASS only.  POT3D_EINVAL otherwise.
  */
 int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);

@@ -282,16 +282,20 @@ bool streams_from_hbm(const pot3d_ctx *c)
     return (double)c->npad * sizeof(double) >= 512.0 * 1024 * 1024;
 }
 
-// The one-sweep kernel addresses a vector with 32-bit byte offsets.
+// The one-sweep kernel addresses a vector with 32-bit byte offsets; it runs
+// the iterations of single solves (FP64, or the FP32 inner iterations of the
+// refined mode), not the server's batched graphs.
 bool sweep_capable(const pot3d_ctx *c)
 {
-    return c->precision == POT3D_FP64 && !c->serving && (double)c->npad * sizeof(double) < 4294967296.0;
+    const double vb = c->precision == POT3D_FP32_REFINED ? sizeof(float) : sizeof(double);
+    return !c->serving && (double)c->npad * vb < 4294967296.0;
 }
 
-// FP64 single-solve contexts iterate in one sweep unless set otherwise.
+// Single solves iterate in one sweep unless set otherwise.
 bool one_sweep(const pot3d_ctx *c)
 {
-    return c->graph_s && c->iteration == POT3D_ITER_ONE_SWEEP;
+    return (c->precision == POT3D_FP32_REFINED ? c->graph32s != nullptr : c->graph_s != nullptr) &&
+           c->iteration == POT3D_ITER_ONE_SWEEP;
 }
 
 void choose_launch(pot3d_ctx *c)
@@ -324,7 +328,8 @@ void choose_launch(pot3d_ctx *c)
         const int rows = env_int("POT3D_SWEEP_ROWS", 4);
         c->sweep_rows = valid_sweep_rows(rows) ? rows : 4;
         const int ts = env_int("POT3D_TARGET_BLOCKS_S", 0);
-        const int resident = std::max(1, sweep_blocks_per_cu<double>(c->sweep_rows)) * std::max(1, c->num_cu);
+        const int per_cu = fp32 ? sweep_blocks_per_cu<float>(c->sweep_rows) : sweep_blocks_per_cu<double>(c->sweep_rows);
+        const int resident = std::max(1, per_cu) * std::max(1, c->num_cu);
         c->grid_s = make_sweep_grid(c, c->sweep_rows, ts > 0 ? ts : resident);
         c->grid_s.reverse = env_int("POT3D_REVERSE_S", 0) != 0;
         c->max_blocks = std::max(c->max_blocks, c->grid_s.nblocks);
@@ -407,24 +412,25 @@ int capture_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, DevScalars *sc, h
 // Capture 2 m sweeps of the one-sweep iteration (sweep, finisher) on the
 // idle context stream.  Sweep j reads r and p from buffer j mod 2 and writes
 // buffer (j + 1) mod 2; 2 m is even, so replays continue the alternation.
-int capture_sweeps(pot3d_ctx *c, hipGraphExec_t *out)
+template <typename V>
+int capture_sweeps(pot3d_ctx *c, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc, hipGraphExec_t *out)
 {
     hipStream_t s = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    double *rb[2] = {c->r, c->r2};
-    double *pb[2] = {c->p[0], c->p[1]};
+    V *rb[2] = {r0, r1};
+    V *pb[2] = {p0, p1};
     for (int it = 0; it < 2 * c->graph_m && e == hipSuccess; ++it) {
-        SweepVecs<double> v{};
+        SweepVecs<V> v{};
         v.r_in = rb[it & 1];
         v.r_out = rb[(it + 1) & 1];
         v.p_old = pb[it & 1];
         v.p_new = pb[(it + 1) & 1];
-        v.x = c->x;
-        v.sc = c->sc;
+        v.x = x;
+        v.sc = sc;
         v.partial = c->partial;
-        e = launch_sweep<double>(c->sweep_rows, c->grid_s, v, s);
-        if (e == hipSuccess) e = launch_finish(kFinSweep, c->sc, c->partial, c->grid_s.nblocks, s);
+        e = launch_sweep<V>(c->sweep_rows, c->grid_s, v, s);
+        if (e == hipSuccess) e = launch_finish(kFinSweep, sc, c->partial, c->grid_s.nblocks, s);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &graph);
@@ -476,12 +482,13 @@ void free_ctx(pot3d_ctx *c)
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
     if (c->graph_s) (void)hipGraphExecDestroy(c->graph_s);
+    if (c->graph32s) (void)hipGraphExecDestroy(c->graph32s);
     for (hipEvent_t *e : {&c->ev_poll[0], &c->ev_poll[1], &c->ev_t0, &c->ev_t1, &c->ev_loop0, &c->ev_loop1})
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
                     c->bplane, c->br, c->partial, c->poles, c->sc,
-                    c->r32, c->p32[0], c->p32[1], c->e32, c->sc32};
+                    c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -671,7 +678,9 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         rc = refined_start_inner(c, s, tol, maxit - total, out, outer > 0 ? &inner : nullptr, scale_prev);
         if (rc != POT3D_OK) return rc;
         scale_prev = out.scale;
-        rc = replay_until_done(c, c->graph32, c->sc32, s, maxit - total, c->graph_m, &launches, &inner);
+        const bool sweep = one_sweep(c);
+        rc = replay_until_done(c, sweep ? c->graph32s : c->graph32, c->sc32, s, maxit - total,
+                               sweep ? 2 * c->graph_m : c->graph_m, &launches, &inner);
         if (rc != POT3D_OK) return rc;
         total += inner.k;
         ++outer;
@@ -683,7 +692,8 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         if (rc != POT3D_OK) return rc;
     }
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, 32.0, iters, relres_true);
+    return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, one_sweep(c) ? 24.0 : 32.0, iters,
+                        relres_true);
 }
 
 // The solve proper.  br_dev: device Br (nt*np); phi0: initial guess or NULL
@@ -858,13 +868,27 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
 // Average duration of the one-sweep kernel as it runs in a solve: as
 // time_pair, with a graph of `reps` sweeps (sweep, finisher) of a fixed-count
 // FP64 PCG from x = 0 on the context's right-hand side.
-int time_sweeps(pot3d_ctx *ctx, int reps, double *ms_sweep)
+template <typename V>
+int time_sweeps(pot3d_ctx *ctx, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_sweep)
 {
     hipStream_t s = ctx->stream;
     const int m = std::max(2, reps + (reps & 1));   // even: the buffers alternate across the two replays
-    HIP_TRY(ctx, launch_fill<double>(ctx->x, ctx->npad, 0.0, s));
-    const int rc = start_fp64(ctx, s, 0.0, 1 << 30);
-    if (rc != POT3D_OK) return rc;
+    if constexpr (std::is_same<V, double>::value) {
+        HIP_TRY(ctx, launch_fill<double>(ctx->x, ctx->npad, 0.0, s));
+        const int rc = start_fp64(ctx, s, 0.0, 1 << 30);
+        if (rc != POT3D_OK) return rc;
+    } else {
+        // fixed scalars on whatever the FP32 vectors hold
+        DevScalars st{};
+        st.alpha = 1e-3;
+        st.beta = 0.5;
+        st.rho = 1.0;
+        st.bnorm = 1.0;
+        st.tol = 0.0;
+        st.maxit = 1 << 30;
+        ctx->h_sc[0] = st;
+        HIP_TRY(ctx, hipMemcpyAsync(sc, &ctx->h_sc[0], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    }
     // per sweep: start, end
     std::vector<unsigned long long> init(2 * (size_t)m), stamps(2 * (size_t)m);
     for (int q = 0; q < m; ++q) {
@@ -873,23 +897,23 @@ int time_sweeps(pot3d_ctx *ctx, int reps, double *ms_sweep)
     }
     unsigned long long *d_ts = nullptr;
     HIP_TRY(ctx, hipMalloc(reinterpret_cast<void **>(&d_ts), init.size() * sizeof(unsigned long long)));
-    double *rb[2] = {ctx->r, ctx->r2};
-    double *pb[2] = {ctx->p[0], ctx->p[1]};
+    V *rb[2] = {r0, r1};
+    V *pb[2] = {p0, p1};
     hipGraphExec_t exec = nullptr;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     for (int it = 0; it < m && e == hipSuccess; ++it) {
-        SweepVecs<double> v{};
+        SweepVecs<V> v{};
         v.r_in = rb[it & 1];
         v.r_out = rb[(it + 1) & 1];
         v.p_old = pb[it & 1];
         v.p_new = pb[(it + 1) & 1];
-        v.x = ctx->x;
-        v.sc = ctx->sc;
+        v.x = x;
+        v.sc = sc;
         v.partial = ctx->partial;
         v.ignore_done = 1;
         v.tstamp = d_ts + 2 * it;
-        e = launch_sweep<double>(ctx->sweep_rows, ctx->grid_s, v, s);
-        if (e == hipSuccess) e = launch_finish(kFinSweep, ctx->sc, ctx->partial, ctx->grid_s.nblocks, s);
+        e = launch_sweep<V>(ctx->sweep_rows, ctx->grid_s, v, s);
+        if (e == hipSuccess) e = launch_finish(kFinSweep, sc, ctx->partial, ctx->grid_s.nblocks, s);
     }
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(s, &graph);
@@ -950,7 +974,6 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     c->graph_m += c->graph_m & 1;   // even, so the p buffers alternate consistently across replays
     c->iteration = env_int("POT3D_ITERATION", POT3D_ITER_ONE_SWEEP) == POT3D_ITER_TWO_PASS ? POT3D_ITER_TWO_PASS
                                                                                          : POT3D_ITER_ONE_SWEEP;
-    if (precision != POT3D_FP64) c->iteration = POT3D_ITER_TWO_PASS;
     c->rf.assign(r_faces, r_faces + nr + 1);
     c->tf.assign(t_faces, t_faces + nt + 1);
     c->pf.assign(p_faces, p_faces + np + 1);
@@ -1000,7 +1023,7 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(launch_fill<double>(c->bplane, (long long)nt * c->pitch, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->poles, 2LL * nr, 0.0, c->stream));
     CREATE_TRY(hipMemsetAsync(c->sc, 0, sizeof(DevScalars), c->stream));
-    if (sweep_capable(c)) {
+    if (sweep_capable(c) && precision == POT3D_FP64) {
         CREATE_TRY(dalloc(&c->r2, (size_t)c->npad));
         CREATE_TRY(launch_fill<double>(c->r2, c->npad, 0.0, c->stream));
     }
@@ -1012,7 +1035,9 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
         CREATE_TRY(dalloc(&c->p32[1], (size_t)c->npad));
         CREATE_TRY(dalloc(&c->e32, (size_t)c->npad));
         CREATE_TRY(dalloc(&c->sc32, 1));
-        for (float *b : {c->r32, c->p32[0], c->p32[1], c->e32}) CREATE_TRY(launch_fill<float>(b, c->npad, 0.0f, c->stream));
+        if (sweep_capable(c)) CREATE_TRY(dalloc(&c->r32b, (size_t)c->npad));
+        for (float *b : {c->r32, c->r32b, c->p32[0], c->p32[1], c->e32})
+            if (b) CREATE_TRY(launch_fill<float>(b, c->npad, 0.0f, c->stream));
         CREATE_TRY(hipMemsetAsync(c->sc32, 0, sizeof(DevScalars), c->stream));
         CREATE_TRY(hipStreamSynchronize(c->stream));
     }
@@ -1020,7 +1045,9 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     // The iteration graphs are captured once, on the idle context stream
     // (serving slots iterate inside the server's batched graph instead).
     int gc = serving ? POT3D_OK : capture_iterations<double>(c, c->r, c->p[0], c->p[1], c->x, c->sc, &c->graph);
-    if (gc == POT3D_OK && c->r2) gc = capture_sweeps(c, &c->graph_s);
+    if (gc == POT3D_OK && c->r2) gc = capture_sweeps<double>(c, c->r, c->r2, c->p[0], c->p[1], c->x, c->sc, &c->graph_s);
+    if (gc == POT3D_OK && c->r32b)
+        gc = capture_sweeps<float>(c, c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32, &c->graph32s);
     if (gc == POT3D_OK && precision == POT3D_FP32_REFINED && !serving)
         gc = capture_iterations<float>(c, c->r32, c->p32[0], c->p32[1], c->e32, c->sc32, &c->graph32);
     if (gc != POT3D_OK) {
@@ -1037,7 +1064,7 @@ size_t context_bytes(const pot3d_ctx *c)
     size_t b = (size_t)c->npad * sizeof(double) * (c->r2 ? 5 : 4) + (size_t)c->nt * c->pitch * sizeof(double) +
                (size_t)c->nt * c->np * sizeof(double) + c->rows_h.size() * sizeof(RowCoef) +
                (size_t)kMaxPartials * c->max_blocks * sizeof(double) + (size_t)2 * c->nr * sizeof(double);
-    if (c->precision == POT3D_FP32_REFINED) b += (size_t)c->npad * sizeof(float) * 4;
+    if (c->precision == POT3D_FP32_REFINED) b += (size_t)c->npad * sizeof(float) * (c->r32b ? 5 : 4);
     return b;
 }
 
@@ -1172,7 +1199,8 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     out->n = ctx->n;
     out->pitch = ctx->pitch;
     fill_shape(ctx, *out);
-    out->bytes_per_iter = (ctx->precision == POT3D_FP32_REFINED ? 32.0 : (one_sweep(ctx) ? 48.0 : 64.0)) * (double)ctx->n;
+    const bool fp32 = ctx->precision == POT3D_FP32_REFINED;
+    out->bytes_per_iter = (one_sweep(ctx) ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0)) * (double)ctx->n;
     return POT3D_OK;
 }
 
@@ -1183,10 +1211,14 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
     int rc;
-    if (ctx->precision == POT3D_FP32_REFINED) {
+    if (one_sweep(ctx) && ctx->precision == POT3D_FP32_REFINED) {
+        rc = time_sweeps<float>(ctx, ctx->r32, ctx->r32b, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps,
+                                ms_update_p);
+        *ms_update_r = 0.0;
+    } else if (ctx->precision == POT3D_FP32_REFINED) {
         rc = time_pair<float>(ctx, ctx->r32, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps, ms_update_p, ms_update_r);
     } else if (one_sweep(ctx)) {
-        rc = time_sweeps(ctx, reps, ms_update_p);
+        rc = time_sweeps<double>(ctx, ctx->r, ctx->r2, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p);
         *ms_update_r = 0.0;
     } else {
         rc = time_pair<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p, ms_update_r);
@@ -1204,8 +1236,8 @@ int pot3d_set_iteration(pot3d_ctx *ctx, int iteration)
     if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
     if (iteration != POT3D_ITER_TWO_PASS && iteration != POT3D_ITER_ONE_SWEEP)
         return fail(ctx, POT3D_EINVAL, "iteration must be POT3D_ITER_TWO_PASS or POT3D_ITER_ONE_SWEEP");
-    if (iteration == POT3D_ITER_ONE_SWEEP && !ctx->graph_s)
-        return fail(ctx, POT3D_EINVAL, "the one-sweep iteration is for FP64 contexts with vectors under 4 GiB");
+    if (iteration == POT3D_ITER_ONE_SWEEP && !ctx->graph_s && !ctx->graph32s)
+        return fail(ctx, POT3D_EINVAL, "the one-sweep iteration needs vectors under 4 GiB");
     ctx->iteration = iteration;
     return POT3D_OK;
 }

@@ -55,12 +55,15 @@ struct pot3d_ctx {
     int max_outer = 50;
     int refine_mode = POT3D_REFINE_RELIABLE;
 
-    // FP64 single solves: one sweep (default) or two passes per iteration
+    // Single solves (FP64 iterations, or the FP32 inner iterations of the
+    // refined mode): one sweep (default) or two passes per iteration
     int iteration = POT3D_ITER_ONE_SWEEP;
     int sweep_rows = 4;           // one-sweep kernel: box rows per wavefront
     GridArgs grid_s{};
-    double *r2 = nullptr;         // one-sweep iteration: the second residual buffer
-    hipGraphExec_t graph_s = nullptr;
+    double *r2 = nullptr;         // one-sweep iteration: the second residual buffer (FP64)
+    float *r32b = nullptr;        // ... (FP32 inner iterations)
+    hipGraphExec_t graph_s = nullptr;     // FP64 sweeps
+    hipGraphExec_t graph32s = nullptr;    // FP32 inner sweeps
 
     bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;

@@ -1303,6 +1303,7 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
         sc->alpha = 0.0;
         sc->beta = beta;
         sc->k = 0;
+        sc->sweep = 0;
         sc->zero_solution = 0;
         sc->relres = 1.0;
         sc->status = POT3D_ENOCONV;
@@ -1580,6 +1581,7 @@ hipError_t launch_sweep(int rows, const GridArgs &g, const SweepVecs<V> &v, hipS
     return hipGetLastError();
 }
 template hipError_t launch_sweep<double>(int, const GridArgs &, const SweepVecs<double> &, hipStream_t);
+template hipError_t launch_sweep<float>(int, const GridArgs &, const SweepVecs<float> &, hipStream_t);
 
 template <typename V>
 int sweep_blocks_per_cu(int rows)
@@ -1593,6 +1595,7 @@ int sweep_blocks_per_cu(int rows)
     return n;
 }
 template int sweep_blocks_per_cu<double>(int);
+template int sweep_blocks_per_cu<float>(int);
 
 template <int TJ, typename V>
 hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)

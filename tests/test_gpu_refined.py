@@ -31,15 +31,17 @@ def refined_solve(solver, br, tol, maxit, phi0=None):
     return d_phi.cpu().numpy(), st, it, rr
 
 
+@pytest.mark.parametrize("iteration", [P.ITER_ONE_SWEEP, P.ITER_TWO_PASS], ids=["one_sweep", "two_pass"])
 @pytest.mark.parametrize("case", [GRIDS[2], GRIDS[4], GRIDS[5], GRIDS[6]], ids=label)
-def test_refined_reaches_fp64_residual(case):
+def test_refined_reaches_fp64_residual(case, iteration):
     rf, tf, pf = make_faces(*case)
     br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
     tol = 1e-10
     ref = oracle.solve(rf, tf, pf, br, tol, 100_000)
-    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED, iteration=iteration) as s:
         phi, st, it, rr = refined_solve(s, br, tol, 200_000)
         stats = s.stats()
+    assert stats["iteration"] == iteration
     tr = oracle.true_relres(ref["coef"], ref["b"], phi)
     # rounding floor of computing ||b - A phi|| / ||b|| in FP64 (~64 ulps of |A||phi|)
     floor = 64 * np.finfo(float).eps * np.linalg.norm(abs(oracle.to_sparse(ref["coef"])) @ np.abs(phi).ravel()) \
@@ -69,7 +71,7 @@ def test_refined_small_workload_and_poles():
     no, so = oracle.pole_values(pf, ref["phi"])
     np.testing.assert_allclose(north, no, rtol=0, atol=1e-7 * np.abs(ref["phi"]).max())
     np.testing.assert_allclose(south, so, rtol=0, atol=1e-7 * np.abs(ref["phi"]).max())
-    assert stats["bytes_per_iter"] == 32.0 * SMALL.n
+    assert stats["bytes_per_iter"] == (24.0 if stats["iteration"] == P.ITER_ONE_SWEEP else 32.0) * SMALL.n
 
 
 def test_refined_edge_cases():
@@ -154,8 +156,9 @@ def test_refinement_modes(case):
     with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
         with pytest.raises(P.Pot3dError):
             s.set_refinement_mode(7)
-        # the FP32 inner iteration has the two-pass form only
-        assert P.pot3d_set_iteration(s.ctx, P.ITER_ONE_SWEEP) == P.EINVAL
+        # the FP32 inner iterations take either form
         assert P.pot3d_set_iteration(s.ctx, P.ITER_TWO_PASS) == P.OK
+        assert P.pot3d_set_iteration(s.ctx, P.ITER_ONE_SWEEP) == P.OK
+        assert P.pot3d_set_iteration(s.ctx, 5) == P.EINVAL
     with P.Solver(rf, tf, pf) as s64:
         assert P.pot3d_set_refinement_mode(s64.ctx, P.REFINE_RELIABLE) == P.EINVAL
