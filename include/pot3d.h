@@ -218,9 +218,11 @@ int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
 
 /*
  * The form of the PCG iteration: of the FP64 iterations, or in FP32-refined
- * contexts of the FP32 inner iterations (POT3D_ITER_ONE_SWEEP, the default,
- * or POT3D_ITER_TWO_PASS; the environment variable POT3D_ITERATION = 0 or 1
- * sets the default of new contexts).  Both run the Jacobi-PCG of Sec. 2.3;
+ * contexts of the FP32 inner iterations (POT3D_ITER_ONE_SWEEP or
+ * POT3D_ITER_TWO_PASS).  Default: one sweep, except for FP32-refined contexts
+ * whose FP64 vectors reach 512 MiB, where the FP32 passes stream faster in
+ * two; the environment variable POT3D_ITERATION = 0 or 1 sets the default of
+ * new contexts (and the form of a batching server when it is created).  Both run the Jacobi-PCG of Sec. 2.3;
  * their iterates agree to rounding.  The one-sweep form needs vectors under
  * 4 GiB (FP64: N < 2^29 with the row padding); larger contexts accept
  * POT3D_ITER_TWO_PASS only.  POT3D_EINVAL otherwise.

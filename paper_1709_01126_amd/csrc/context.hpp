@@ -76,6 +76,8 @@ namespace host {
 
 // Record msg as the context's (or, for ctx = NULL, the thread's) last error.
 int fail(pot3d_ctx *ctx, int code, const std::string &msg);
+// Integer environment variable, or dflt if unset or not a number.
+int env_int(const char *name, int dflt);
 
 #define HIP_TRY(ctx, call)                                                                   \
     do {                                                                                     \

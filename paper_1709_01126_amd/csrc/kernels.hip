@@ -380,12 +380,12 @@ stencil_march(GridArgs g, StencilVecs<V> v, const RowCoef *__restrict__ rows, co
 }
 
 // Index of the slot that owns workgroup bid of a batched launch, or -1.
-template <typename V>
-__device__ __forceinline__ int batch_slot(const BatchSlot<V> *__restrict__ slots, int nslots, int bid)
+template <typename S>
+__device__ __forceinline__ int batch_slot(const S *__restrict__ slots, int nslots, int bid)
 {
     int s = -1;
     for (int q = 0; q < nslots; ++q) {
-        const BatchSlot<V> &sl = slots[q];
+        const S &sl = slots[q];
         if (sl.active && bid >= sl.offset && bid < sl.offset + sl.g.nblocks) s = q;
     }
     return s;
@@ -1111,6 +1111,19 @@ stencil_sweep(GridArgs g, SweepVecs<V> v, const RowCoef *__restrict__ rows, cons
     sweep_body<R, V>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
 }
 
+// Batched sweeps: slot q owns workgroups [offset, offset + nblocks) of the
+// grid and runs exactly the arithmetic of its single-solve launch.
+template <int R, typename V>
+__global__ void __launch_bounds__(kThreads)
+stencil_sweep_batch(const BatchSweep<V> *__restrict__ slots, int nslots)
+{
+    const int bid = blockIdx.x;
+    const int s = batch_slot(slots, nslots, bid);
+    if (s < 0) return;
+    const BatchSweep<V> sl = slots[s];
+    sweep_body<R, V>(sl.g, sl.v, sl.g.rows, sl.v.r_in, sl.v.r_out, sl.v.p_old, sl.v.p_new, sl.v.x, bid - sl.offset);
+}
+
 // ---------------------------------------------------------------------------
 // Finishers: one workgroup sums the per-workgroup partials in a fixed order
 // and advances the scalar state of the iteration.
@@ -1119,20 +1132,32 @@ constexpr int kFinThreads = 256;
 
 __device__ __forceinline__ void block_sums(const double *partial, int nb, int ncomp, double out[kMaxPartials])
 {
-    __shared__ double sh[kMaxPartials][kFinThreads];
+    // Fixed order: each thread sums its strided partials, a wavefront
+    // butterfly combines the 64 lanes, then the 4 wavefronts in order.
+    __shared__ double sh[kFinThreads / kWave][kMaxPartials];
     const int t = threadIdx.x;
-    for (int c = 0; c < ncomp; ++c) {
-        double s = 0.0;
-        for (int q = t; q < nb; q += kFinThreads) s += partial[(long long)c * nb + q];
-        sh[c][t] = s;
+    double acc[kMaxPartials];
+#pragma unroll
+    for (int c = 0; c < kMaxPartials; ++c) {
+        acc[c] = 0.0;
+        if (c < ncomp)
+            for (int q = t; q < nb; q += kFinThreads) acc[c] += partial[(long long)c * nb + q];
     }
+#pragma unroll
+    for (int c = 0; c < kMaxPartials; ++c)
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) acc[c] += __shfl_xor(acc[c], off, kWave);
+    if ((t & (kWave - 1)) == 0)
+#pragma unroll
+        for (int c = 0; c < kMaxPartials; ++c) sh[t / kWave][c] = acc[c];
     __syncthreads();
-    for (int st = kFinThreads / 2; st > 0; st >>= 1) {
-        if (t < st)
-            for (int c = 0; c < ncomp; ++c) sh[c][t] += sh[c][t + st];
-        __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kMaxPartials; ++c) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kFinThreads / kWave; ++w) v += sh[w][c];
+        out[c] = v;
     }
-    for (int c = 0; c < ncomp; ++c) out[c] = sh[c][0];
 }
 
 __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const double *partial, int nb)
@@ -1596,6 +1621,22 @@ int sweep_blocks_per_cu(int rows)
 }
 template int sweep_blocks_per_cu<double>(int);
 template int sweep_blocks_per_cu<float>(int);
+
+template <typename V>
+hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, hipStream_t s)
+{
+    if (total_blocks <= 0) return hipSuccess;
+    const dim3 grid(total_blocks), block(kThreads);
+    switch (rows) {
+    case 4: stencil_sweep_batch<4, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case 6: stencil_sweep_batch<6, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case 8: stencil_sweep_batch<8, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+template hipError_t launch_sweep_batch<double>(int, const BatchSweep<double> *, int, int, hipStream_t);
+template hipError_t launch_sweep_batch<float>(int, const BatchSweep<float> *, int, int, hipStream_t);
 
 template <int TJ, typename V>
 hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)

@@ -45,6 +45,9 @@ template <typename V>
 hipError_t launch_sweep(int rows, const GridArgs &g, const SweepVecs<V> &v, hipStream_t s);
 template <typename V>
 int sweep_blocks_per_cu(int rows);
+// Batched sweeps over a device slot table (every active slot runs `rows`).
+template <typename V>
+hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, hipStream_t s);
 inline bool valid_sweep_rows(int rows) { return rows == 4 || rows == 6 || rows == 8; }
 
 // Checked builds: the source line of the first out-of-range index seen since

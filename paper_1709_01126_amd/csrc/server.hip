@@ -15,7 +15,10 @@
 //      speed up, run alone.  Per-grid contexts (tables and vectors) are
 //      cached and reused; idle ones are evicted oldest first when the budget
 //      needs it;
-//   3. queues one replay of a captured graph of m batched PCG iterations.
+//   3. queues one replay of a captured graph of m batched PCG iterations (in
+//      the one-sweep form, the default: 2m sweeps of one batched sweep and one
+//      finisher each; in the two-pass form m iterations of two batched passes
+//      and two finishers; the form is fixed when the server is created).
 //      Each kernel of it covers every active slot (a slot table in device
 //      memory maps workgroups to slots), and slots that have converged are
 //      masked by their own done flags.
@@ -24,11 +27,11 @@
 // slot that finished in replay k runs through replay k+1 as a no-op, and
 // retirement and admission are ordered after it on the same stream.
 // The graphs read the slot tables at run time, so requests join and leave
-// between replays without recapture; one graph is captured per pair of launch
-// widths the first time a batch needs it.  Every slot
-// runs exactly the launch shape, tile order and reduction order of a single
-// solve on the same grid, so each result is bitwise the one the request gets
-// from pot3d_solve.
+// between replays without recapture; one graph is captured per launch width
+// (pair of widths in the two-pass form) the first time a batch needs it.
+// Every slot runs exactly the launch shape, tile order and reduction order of
+// a single solve on the same grid in the same form, so each result is
+// bitwise the one the request gets from pot3d_solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -96,6 +99,8 @@ int round_up(int v, int a) { return (v + a - 1) / a * a; }
 struct pot3d_server {
     int device = 0, precision = POT3D_FP64, max_slots = 0, graph_m = 16;
     int tile_p = kTileMarch8, tile_r = kTileMarch8;   // launch shapes of every slot
+    bool sweep = true;       // one-sweep batches (else two passes)
+    int sweep_rows = 4;      // box rows per wavefront of every slot's sweep kernel
     size_t budget = 0, used = 0;
     size_t cache_budget = size_t(256) << 20;   // bytes streamed per iteration by the active set
     hipStream_t stream = nullptr, capture_stream = nullptr;
@@ -112,12 +117,17 @@ struct pot3d_server {
     std::vector<BatchSlot<double>> h_p64[2], h_r64[2];
     std::vector<BatchSlot<float>> h_p32[2], h_r32[2];
     std::vector<BatchFin> h_finp, h_finr;
+    // one-sweep slot tables [parity][slot] (the finishers use d_finp)
+    BatchSweep<double> *d_s64[2] = {nullptr, nullptr};
+    BatchSweep<float> *d_s32[2] = {nullptr, nullptr};
+    std::vector<BatchSweep<double>> h_s64[2];
+    std::vector<BatchSweep<float>> h_s32[2];
     DevScalars *h_status = nullptr;   // pinned, [2][slot]: statuses after the two latest replays
     Replay replay[2];
     int last = -1;                    // replay buffer of the most recent launch
     std::vector<BatchGraph> graphs;   // captured batched graphs by launch widths
     unsigned long long graph_clock = 0;
-    int need_p = 0, need_r = 0;   // workgroups the active slots own in each pass
+    int need_p = 0, need_r = 0;   // workgroups the active slots own in each pass (need_p: the sweep)
     std::chrono::steady_clock::time_point t0;
     std::string err;
 
@@ -156,13 +166,20 @@ hipError_t dalloc(T **p, size_t count)
 }
 
 template <typename V>
-int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr, int wp, int wr,
-                    hipGraphExec_t *out)
+int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *const *dr, BatchSweep<V> *const *ds,
+                    int wp, int wr, hipGraphExec_t *out)
 {
     hipStream_t s = sv->capture_stream;
     SV_TRY(sv, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int it = 0; it < sv->graph_m && e == hipSuccess; ++it) {
+    if (sv->sweep) {
+        // 2m sweeps: the parity of the r and p buffers continues across replays
+        for (int it = 0; it < 2 * sv->graph_m && e == hipSuccess; ++it) {
+            e = launch_sweep_batch<V>(sv->sweep_rows, ds[it & 1], sv->max_slots, wp, s);
+            if (e == hipSuccess) e = launch_finish_batch(kFinSweep, sv->d_finp, sv->max_slots, s);
+        }
+    }
+    for (int it = 0; !sv->sweep && it < sv->graph_m && e == hipSuccess; ++it) {
         e = launch_stencil_batch<V>(kUpdateP, sv->tile_p, dp[it & 1], sv->max_slots, wp, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinSigma, sv->d_finp, sv->max_slots, s);
         if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, sv->tile_r, dr[it & 1], sv->max_slots, wr, s);
@@ -206,8 +223,8 @@ int graph_for(pot3d_server *sv, int wp, int wr, hipGraphExec_t *out)
         sv->graphs.erase(sv->graphs.begin() + oldest);
     }
     hipGraphExec_t g = nullptr;
-    const int rc = sv->precision == POT3D_FP64 ? capture_batched<double>(sv, sv->d_p64, sv->d_r64, wp, wr, &g)
-                                               : capture_batched<float>(sv, sv->d_p32, sv->d_r32, wp, wr, &g);
+    const int rc = sv->precision == POT3D_FP64 ? capture_batched<double>(sv, sv->d_p64, sv->d_r64, sv->d_s64, wp, wr, &g)
+                                               : capture_batched<float>(sv, sv->d_p32, sv->d_r32, sv->d_s32, wp, wr, &g);
     if (rc != POT3D_OK) return rc;
     sv->graphs.push_back(BatchGraph{wp, wr, ++sv->graph_clock, g});
     *out = g;
@@ -216,7 +233,8 @@ int graph_for(pot3d_server *sv, int wp, int wr, hipGraphExec_t *out)
 
 // Slot tables from the current slots (inactive slots own no workgroups).
 template <typename V>
-void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<BatchSlot<V>> *hr)
+void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<BatchSlot<V>> *hr,
+                 std::vector<BatchSweep<V>> *hs)
 {
     int offp = 0, offr = 0;
     for (int q = 0; q < sv->max_slots; ++q) {
@@ -224,25 +242,47 @@ void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<Ba
         for (int par = 0; par < 2; ++par) {
             hp[par][q] = BatchSlot<V>{};
             hr[par][q] = BatchSlot<V>{};
+            hs[par][q] = BatchSweep<V>{};
         }
         sv->h_finp[q] = BatchFin{};
         sv->h_finr[q] = BatchFin{};
         if (!sl.active) continue;
         pot3d_ctx *c = sl.ctx;
-        V *r, *x, *p[2];
+        V *r, *r2, *x, *p[2];
         DevScalars *sc;
         if constexpr (std::is_same<V, double>::value) {
             r = c->r;
+            r2 = c->r2;
             x = c->x;
             p[0] = c->p[0];
             p[1] = c->p[1];
             sc = c->sc;
         } else {
             r = c->r32;
+            r2 = c->r32b;
             x = c->e32;
             p[0] = c->p32[0];
             p[1] = c->p32[1];
             sc = c->sc32;
+        }
+        if (sv->sweep) {
+            V *rb[2] = {r, r2};
+            for (int par = 0; par < 2; ++par) {
+                BatchSweep<V> &a = hs[par][q];
+                a.g = c->grid_s;
+                a.v.r_in = rb[par];
+                a.v.r_out = rb[par ^ 1];
+                a.v.p_old = p[par];
+                a.v.p_new = p[par ^ 1];
+                a.v.x = x;
+                a.v.sc = sc;
+                a.v.partial = c->partial;
+                a.offset = offp;
+                a.active = 1;
+            }
+            sv->h_finp[q] = BatchFin{sc, c->partial, c->grid_s.nblocks, 1};
+            offp += round_up(c->grid_s.nblocks, kBlockAlign);
+            continue;
         }
         for (int par = 0; par < 2; ++par) {
             BatchSlot<V> &a = hp[par][q];
@@ -280,19 +320,23 @@ int upload_tables(pot3d_server *sv)
     hipStream_t s = sv->stream;
     const size_t n = sv->max_slots;
     if (sv->precision == POT3D_FP64) {
-        fill_tables<double>(sv, sv->h_p64, sv->h_r64);
+        fill_tables<double>(sv, sv->h_p64, sv->h_r64, sv->h_s64);
         for (int par = 0; par < 2; ++par) {
             SV_TRY(sv, hipMemcpyAsync(sv->d_p64[par], sv->h_p64[par].data(), n * sizeof(BatchSlot<double>),
                                       hipMemcpyHostToDevice, s));
             SV_TRY(sv, hipMemcpyAsync(sv->d_r64[par], sv->h_r64[par].data(), n * sizeof(BatchSlot<double>),
                                       hipMemcpyHostToDevice, s));
+            SV_TRY(sv, hipMemcpyAsync(sv->d_s64[par], sv->h_s64[par].data(), n * sizeof(BatchSweep<double>),
+                                      hipMemcpyHostToDevice, s));
         }
     } else {
-        fill_tables<float>(sv, sv->h_p32, sv->h_r32);
+        fill_tables<float>(sv, sv->h_p32, sv->h_r32, sv->h_s32);
         for (int par = 0; par < 2; ++par) {
             SV_TRY(sv, hipMemcpyAsync(sv->d_p32[par], sv->h_p32[par].data(), n * sizeof(BatchSlot<float>),
                                       hipMemcpyHostToDevice, s));
             SV_TRY(sv, hipMemcpyAsync(sv->d_r32[par], sv->h_r32[par].data(), n * sizeof(BatchSlot<float>),
+                                      hipMemcpyHostToDevice, s));
+            SV_TRY(sv, hipMemcpyAsync(sv->d_s32[par], sv->h_s32[par].data(), n * sizeof(BatchSweep<float>),
                                       hipMemcpyHostToDevice, s));
         }
     }
@@ -303,12 +347,14 @@ int upload_tables(pot3d_server *sv)
     return POT3D_OK;
 }
 
-// Bytes one iteration of a request streams: FP64 x, r and two directions, or
-// in refined mode the four FP32 vectors of the inner solve.
+// Bytes one iteration of a request streams: FP64 x, r and two directions (and
+// the second r of the one-sweep form), or in refined mode the FP32 vectors of
+// the inner solve.
 size_t stream_bytes(const pot3d_server *sv, const Request *r)
 {
     const size_t pitch = (size_t)(r->np + 7) / 8 * 8;
-    return (size_t)r->nr * r->nt * pitch * (sv->precision == POT3D_FP32_REFINED ? 16 : 32);
+    const size_t vectors = sv->sweep ? 5 : 4;
+    return (size_t)r->nr * r->nt * pitch * vectors * (sv->precision == POT3D_FP32_REFINED ? 4 : 8);
 }
 
 bool same_grid(const pot3d_ctx *c, const Request *r)
@@ -341,9 +387,11 @@ int acquire_context(pot3d_server *sv, Request *r, pot3d_ctx **ctx)
             return POT3D_OK;
         }
     }
-    // estimate before allocating: 4 FP64 vectors (+4 FP32) of the padded size, plus tables
+    // estimate before allocating: 4 FP64 vectors (+4 or 5 FP32 in refined mode,
+    // +1 FP64 in the FP64 one-sweep form) of the padded size, plus tables
     const long long pitch = (r->np + 7) / 8 * 8;
-    const size_t need = (size_t)r->nr * r->nt * pitch * (sv->precision == POT3D_FP32_REFINED ? 48 : 32) +
+    const size_t per_cell = sv->precision == POT3D_FP32_REFINED ? (sv->sweep ? 52 : 48) : (sv->sweep ? 40 : 32);
+    const size_t need = (size_t)r->nr * r->nt * pitch * per_cell +
                         (size_t)r->nr * r->nt * 64 + (size_t)r->nt * pitch * 16 + (1u << 20);
     while (sv->used + need > sv->budget && !sv->idle.empty()) evict_one(sv);
     if (sv->used + need > sv->budget) return POT3D_OK;   // wait for a slot to retire
@@ -351,7 +399,8 @@ int acquire_context(pot3d_server *sv, Request *r, pot3d_ctx **ctx)
     int rc = create_context(r->rf.data(), r->nr, r->tf.data(), r->nt, r->pf.data(), r->np, POT3D_UPPER_SOURCE_SURFACE,
                             sv->precision, sv->device, true, &c);
     if (rc != POT3D_OK) return sfail(sv, rc, pot3d_last_error(nullptr));
-    if (c->tile_p != sv->tile_p || c->tile_r != sv->tile_r) {
+    if (c->tile_p != sv->tile_p || c->tile_r != sv->tile_r || c->sweep_rows != sv->sweep_rows ||
+        (sv->sweep && (c->precision == POT3D_FP64 ? !c->r2 : !c->r32b))) {
         free_ctx(c);
         return sfail(sv, POT3D_EINVAL, "context launch shape differs from the server's batched kernels");
     }
@@ -387,8 +436,10 @@ int retire(pot3d_server *sv, Slot &sl, DevScalars fin, int total_iters, int oute
     int iters = 0;
     double rel = 0.0;
     SV_TRY(sv, hipEventRecord(c->ev_loop1, sv->stream));
+    const bool fp32 = sv->precision == POT3D_FP32_REFINED;
+    const double per_unknown = sv->sweep ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0);
     const int rc = finish_solve(c, dst, hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
-                                sv->precision == POT3D_FP32_REFINED ? 32.0 : 64.0, &iters, &rel);
+                                per_unknown, &iters, &rel);
     if (rc != POT3D_OK && rc != POT3D_ENOCONV && rc != POT3D_EBREAKDOWN) return sfail(sv, rc, pot3d_last_error(c));
     complete(sv, sl, rc, iters, outer, rel);
     return POT3D_OK;
@@ -467,12 +518,17 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return sfail(nullptr, POT3D_EDEVICE, "hipMemGetInfo failed");
     sv->budget = hbm_budget_bytes > 0.0 ? (size_t)hbm_budget_bytes : (size_t)(0.8 * (double)free_b);
     default_tiles(precision, &sv->tile_p, &sv->tile_r);
+    sv->sweep = env_int("POT3D_ITERATION", POT3D_ITER_ONE_SWEEP) != POT3D_ITER_TWO_PASS;
+    const int rows = env_int("POT3D_SWEEP_ROWS", 4);
+    sv->sweep_rows = valid_sweep_rows(rows) ? rows : 4;
     sv->slots.assign(max_slots, Slot{});
     for (int par = 0; par < 2; ++par) {
         sv->h_p64[par].assign(max_slots, BatchSlot<double>{});
         sv->h_r64[par].assign(max_slots, BatchSlot<double>{});
         sv->h_p32[par].assign(max_slots, BatchSlot<float>{});
         sv->h_r32[par].assign(max_slots, BatchSlot<float>{});
+        sv->h_s64[par].assign(max_slots, BatchSweep<double>{});
+        sv->h_s32[par].assign(max_slots, BatchSweep<float>{});
     }
     sv->h_finp.assign(max_slots, BatchFin{});
     sv->h_finr.assign(max_slots, BatchFin{});
@@ -492,9 +548,11 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
         if (precision == POT3D_FP64) {
             e = dalloc(&p->d_p64[par], max_slots);
             if (e == hipSuccess) e = dalloc(&p->d_r64[par], max_slots);
+            if (e == hipSuccess) e = dalloc(&p->d_s64[par], max_slots);
         } else {
             e = dalloc(&p->d_p32[par], max_slots);
             if (e == hipSuccess) e = dalloc(&p->d_r32[par], max_slots);
+            if (e == hipSuccess) e = dalloc(&p->d_s32[par], max_slots);
         }
     }
     if (e == hipSuccess) e = dalloc(&p->d_finp, max_slots);
@@ -511,7 +569,7 @@ int pot3d_server_create(int device, int precision, int max_slots, double hbm_bud
     }
     // one graph now, so that capture problems show here
     hipGraphExec_t g0 = nullptr;
-    const int rc = graph_for(p, kBlockAlign, kBlockAlign, &g0);
+    const int rc = graph_for(p, kBlockAlign, p->sweep ? 0 : kBlockAlign, &g0);
     if (rc != POT3D_OK) {
         g_server_error = p->err;
         return bail(rc);
@@ -728,7 +786,8 @@ void pot3d_server_destroy(pot3d_server *sv)
     for (auto &g : sv->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     void *bufs[] = {sv->d_p64[0], sv->d_p64[1], sv->d_r64[0], sv->d_r64[1], sv->d_p32[0], sv->d_p32[1],
-                    sv->d_r32[0], sv->d_r32[1], sv->d_finp, sv->d_finr};
+                    sv->d_r32[0], sv->d_r32[1], sv->d_s64[0], sv->d_s64[1], sv->d_s32[0], sv->d_s32[1],
+                    sv->d_finp, sv->d_finr};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (sv->h_status) (void)hipHostFree(sv->h_status);

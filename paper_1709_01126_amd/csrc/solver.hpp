@@ -115,6 +115,15 @@ struct BatchSlot {
     int active;
 };
 
+// One slot of a batched one-sweep launch (device-resident table).
+template <typename V>
+struct BatchSweep {
+    GridArgs g;
+    SweepVecs<V> v;
+    int offset;   // first workgroup of the slot in the batched grid (multiple of 8)
+    int active;
+};
+
 // One slot of a batched finisher launch.
 struct BatchFin {
     DevScalars *sc;

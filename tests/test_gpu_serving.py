@@ -3,8 +3,9 @@
 Bars:
 * every result of the server is bitwise the one pot3d_solve returns for the
   same request on its own (same Phi, iteration count, status and true
-  residual), in FP64 and FP32-refined mode, whatever else shares the GPU (the
-  server iterates in the two-pass form, so FP64 single solves are set to it);
+  residual), in FP64 and FP32-refined mode and in both iteration forms
+  (POT3D_ITERATION, read when the server and the contexts are created),
+  whatever else shares the GPU;
 * every FP64 result meets the single-solve parity bar against the oracle:
   ||Phi - Phi_orc|| <= 1e-8 ||Phi_orc|| at tol 1e-10;
 * admission honours the slot count and the device-memory budget, and the
@@ -39,7 +40,7 @@ def requests(cases, tol=1e-10, maxit=100_000, seed0=11):
 def alone(reqs, precision):
     res = []
     for case, rf, tf, pf, br, tol, maxit in reqs:
-        with P.Solver(rf, tf, pf, precision=precision, iteration=P.ITER_TWO_PASS) as s:
+        with P.Solver(rf, tf, pf, precision=precision) as s:
             phi, st, it, rr = s.solve(br, tol, maxit)
         res.append((phi, st, it, rr))
     return res
@@ -59,12 +60,14 @@ def run_server(reqs, precision, max_slots, budget=0.0, max_steps=100_000):
     return out, peak_active, stats
 
 
+@pytest.mark.parametrize("form", ["1", "0"], ids=["one_sweep", "two_pass"])
 @pytest.mark.parametrize("precision", [P.FP64, P.FP32_REFINED], ids=["fp64", "fp32_refined"])
-def test_server_results_equal_single_solves(precision):
+def test_server_results_equal_single_solves(precision, form, monkeypatch):
+    monkeypatch.setenv("POT3D_ITERATION", form)
     reqs = requests(MIX)
     ref = alone(reqs, precision)
     out, peak, stats = run_server(reqs, precision, max_slots=3)
-    print(f"\n[serving] {'fp64' if precision == P.FP64 else 'refined'}: {len(reqs)} requests, 3 slots, "
+    print(f"\n[serving] {'fp64' if precision == P.FP64 else 'refined'} form {form}: {len(reqs)} requests, 3 slots, "
           f"{stats['replays']} replays, peak active {peak}, cached contexts {stats['cached_contexts']}", flush=True)
     assert peak == 3
     for (case, *_), (phi_a, st_a, it_a, rr_a), (phi_s, info) in zip(reqs, ref, out):
@@ -138,7 +141,7 @@ def test_server_edge_cases():
     assert res["inf"][1]["status"] == P.EBREAKDOWN and res["inf"][1]["iters"] == 0
     assert res["maxit0"][1]["status"] == P.ENOCONV and res["maxit0"][1]["iters"] == 0
     assert res["fixed"][1]["status"] == P.ENOCONV and res["fixed"][1]["iters"] == 37
-    with P.Solver(rf, tf, pf, iteration=P.ITER_TWO_PASS) as s:
+    with P.Solver(rf, tf, pf) as s:
         for key, (b, tol, maxit) in {"cap": (br, 1e-10, 5), "fixed": (br, 0.0, 37)}.items():
             phi_a, st_a, it_a, _ = s.solve(b, tol, maxit)
             assert np.array_equal(res[key][0], phi_a) and res[key][1]["iters"] == it_a
