@@ -54,6 +54,12 @@ def _load():
         i = ctypes.c_int
         lib.orc_assemble.argtypes = [d, i, d, i, d, i, d]
         lib.orc_assemble.restype = i
+        lib.orc_assemble_bc.argtypes = [d, i, d, i, d, i, i, d]
+        lib.orc_assemble_bc.restype = i
+        lib.orc_rhs_bc.argtypes = [d, i, d, i, d, i, i, d, d, d]
+        lib.orc_rhs_bc.restype = None
+        lib.orc_gauge.argtypes = [d, i, d, i, d, i, d]
+        lib.orc_gauge.restype = None
         lib.orc_matvec.argtypes = [i, i, i, d, d, d]
         lib.orc_matvec.restype = None
         lib.orc_rhs.argtypes = [d, i, d, i, d, i, d, d]
@@ -80,12 +86,13 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def assemble(rf, tf, pf) -> np.ndarray:
-    """Coefficient arrays (8, nr, nt, np): diag, W_r-, W_r+, W_t-, W_t+, W_p-, W_p+, D_top."""
+def assemble(rf, tf, pf, closed_wall: bool = False) -> np.ndarray:
+    """Coefficient arrays (8, nr, nt, np): diag, W_r-, W_r+, W_t-, W_t+, W_p-, W_p+, D_top.
+    closed_wall: Br = 0 on r = R1 (D_top = 0) instead of Phi = 0 there."""
     rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
     nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
     coef = np.empty((NCOEF, nr, nt, np_))
-    st = _load().orc_assemble(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(coef))
+    st = _load().orc_assemble_bc(_p(rf), nr, _p(tf), nt, _p(pf), np_, int(bool(closed_wall)), _p(coef))
     if st != OK:
         raise RuntimeError(f"orc_assemble failed: {st}")
     return coef
@@ -99,13 +106,27 @@ def matvec(coef: np.ndarray, x: np.ndarray) -> np.ndarray:
     return y
 
 
-def rhs(rf, tf, pf, br) -> np.ndarray:
+def rhs(rf, tf, pf, br, closed_wall: bool = False, return_monopole: bool = False):
+    """b from Br on r = R0; with closed_wall the area-weighted mean of Br (the
+    monopole, which a closed shell cannot carry) is removed first."""
     rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
     nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
     br = _f64(br).reshape(nt, np_)
     b = np.empty((nr, nt, np_))
-    _load().orc_rhs(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(br), _p(b))
-    return b
+    mono = ctypes.c_double(0.0)
+    if closed_wall:
+        _load().orc_rhs_bc(_p(rf), nr, _p(tf), nt, _p(pf), np_, 1, _p(br), _p(b), ctypes.byref(mono))
+    else:
+        _load().orc_rhs(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(br), _p(b))
+    return (b, mono.value) if return_monopole else b
+
+
+def gauge(rf, tf, pf, x) -> np.ndarray:
+    """Closed wall: x minus its cell-volume-weighted mean over the shell."""
+    rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
+    x = _f64(x).copy()
+    _load().orc_gauge(_p(rf), rf.size - 1, _p(tf), tf.size - 1, _p(pf), pf.size - 1, _p(x))
+    return x
 
 
 def dot(a: np.ndarray, b: np.ndarray) -> float:
@@ -141,11 +162,15 @@ def pole_values(pf, x: np.ndarray):
     return n, s
 
 
-def solve(rf, tf, pf, br, tol: float, maxit: int, x0=None):
-    """Assemble, form b and run PCG.  Returns dict with phi, iters, relres, true_relres, status."""
-    coef = assemble(rf, tf, pf)
-    b = rhs(rf, tf, pf, br)
+def solve(rf, tf, pf, br, tol: float, maxit: int, x0=None, closed_wall: bool = False):
+    """Assemble, form b and run PCG.  Returns dict with phi, iters, relres, true_relres, status.
+    closed_wall: Br = 0 on r = R1; the monopole of Br is removed from b and
+    the solution is returned with zero cell-volume-weighted mean."""
+    coef = assemble(rf, tf, pf, closed_wall)
+    b = rhs(rf, tf, pf, br, closed_wall)
     x, iters, relres, st = pcg(coef, b, tol, maxit, x0)
+    if closed_wall:
+        x = gauge(rf, tf, pf, x)
     return {"phi": x, "iters": iters, "relres": relres, "status": st,
             "true_relres": true_relres(coef, b, x) if np.any(b) else 0.0, "coef": coef, "b": b}
 

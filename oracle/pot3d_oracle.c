@@ -12,7 +12,10 @@
  *    shell R0 <= r <= R1, with
  *      * the surface condition eq. (2) on r = R0, read here with the sign
  *        dPhi/dr = -Br (so B = -grad Phi); the paper's +Br convention gives -Phi;
- *      * the "source surface" condition Phi = 0 on r = R1;
+ *      * the "source surface" condition Phi = 0 on r = R1, or the "closed wall"
+ *        Br = 0 on r = R1 (no flux through the top face; the system is then
+ *        singular, with the constants as its null space: see orc_rhs_bc and
+ *        orc_gauge);
  *      * periodicity in phi;
  *      * the polar condition eq. (3), which only defines the value reported at
  *        the poles (see orc_pole_values).
@@ -69,12 +72,14 @@ static long idx3(int i, int j, int k, int nt, int np) { return ((long)i * nt + j
  *   bottom face r = R0: no coupling (Neumann data go to b)
  *   top face r = R1, Phi = 0 on the face, one-sided difference over the half cell:
  *       Dtop = dphi_k * sin(theta_j) dtheta_j * rf[nr]^2 / (rf[nr] - r_{nr-1}), on the diagonal
+ *       (closed wall, Br = 0 on the face: no flux, Dtop = 0)
  *   polar-angle face j+1/2:  W = dphi_k * dr_i * sin(tf[j+1]) / (theta_{j+1} - theta_j)
  *   pole faces (theta = 0, pi): sin = 0, so no coupling (set exactly to zero)
  *   azimuthal face k+1/2:    W = dr_i * dtheta_j / sin(theta_j) / (phi_{k+1} - phi_k)
  *   diagonal = sum of the neighbour weights present + Dtop
  * ------------------------------------------------------------------------- */
-int orc_assemble(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, double *coef)
+int orc_assemble_bc(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int closed_wall,
+                    double *coef)
 {
     if (nr < 1 || nt < 1 || np < 1 || !rf || !tf || !pf || !coef) return ORC_EINVAL;
     const long N = (long)nr * nt * np;
@@ -102,7 +107,7 @@ int orc_assemble(const double *rf, int nr, const double *tf, int nt, const doubl
                 double wrm = 0.0, wrp = 0.0, wtm = 0.0, wtp = 0.0, dtop = 0.0;
                 if (i > 0)      wrm = area_r * rf[i] * rf[i] / (rc[i] - rc[i - 1]);
                 if (i < nr - 1) wrp = area_r * rf[i + 1] * rf[i + 1] / (rc[i + 1] - rc[i]);
-                if (i == nr - 1) dtop = area_r * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]);
+                if (i == nr - 1 && !closed_wall) dtop = area_r * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]);
                 if (j > 0)      wtm = dp[k] * dr[i] * sin(tf[j]) / (tc[j] - tc[j - 1]);
                 if (j < nt - 1) wtp = dp[k] * dr[i] * sin(tf[j + 1]) / (tc[j + 1] - tc[j]);
                 double sp_minus = (k > 0) ? pc[k] - pc[k - 1] : pc[0] + ORC_TWO_PI - pc[np - 1];
@@ -121,6 +126,11 @@ int orc_assemble(const double *rf, int nr, const double *tf, int nt, const doubl
     }
     free(rc); free(dr); free(tc); free(dt); free(pc); free(dp);
     return ORC_OK;
+}
+
+int orc_assemble(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, double *coef)
+{
+    return orc_assemble_bc(rf, nr, tf, nt, pf, np, 0, coef);
 }
 
 /* y = A x: diagonal times the centre minus each neighbour weight times that
@@ -172,6 +182,74 @@ void orc_rhs(const double *rf, int nr, const double *tf, int nt, const double *p
             b[idx3(0, j, k, nt, np)] = dpk * sin(tcj) * dtj * rf[0] * rf[0] * br[(long)j * np + k];
         }
     }
+}
+
+/* Closed wall: the shell then has no outlet, so the flux of B through r = R0
+ * must vanish (Gauss's law for div B = 0), which is also the solvability
+ * condition sum(b) = 0 of the singular system.  The surface data's monopole,
+ * the area-weighted mean of Br over r = R0 (weights dphi_k sin(theta_j)
+ * dtheta_j), is removed first; *mono receives it.  Data that are a monopole
+ * up to rounding (the weighted 2-norm of Br - mean at most 1e-14 of that of
+ * Br) give b = 0, so Phi = 0. */
+void orc_rhs_bc(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int closed_wall,
+                const double *br, double *b, double *mono)
+{
+    double m = 0.0, keep = 1.0;
+    if (closed_wall) {
+        double num = 0.0, den = 0.0;
+        for (int j = 0; j < nt; j++) {
+            const double tcj = 0.5 * (tf[j] + tf[j + 1]), dtj = tf[j + 1] - tf[j];
+            for (int k = 0; k < np; k++) {
+                const double w = (pf[k + 1] - pf[k]) * sin(tcj) * dtj;
+                num += w * br[(long)j * np + k];
+                den += w;
+            }
+        }
+        m = num / den;
+        double raw = 0.0, rest = 0.0;
+        for (int j = 0; j < nt; j++) {
+            const double tcj = 0.5 * (tf[j] + tf[j + 1]), dtj = tf[j + 1] - tf[j];
+            for (int k = 0; k < np; k++) {
+                const double w = (pf[k + 1] - pf[k]) * sin(tcj) * dtj;
+                const double v = br[(long)j * np + k];
+                raw += (w * v) * (w * v);
+                rest += (w * (v - m)) * (w * (v - m));
+            }
+        }
+        if (rest <= 1e-28 * raw) keep = 0.0;
+    }
+    if (mono) *mono = m;
+    const long N = (long)nr * nt * np;
+    memset(b, 0, sizeof(double) * N);
+    for (int j = 0; j < nt; j++) {
+        const double tcj = 0.5 * (tf[j] + tf[j + 1]), dtj = tf[j + 1] - tf[j];
+        for (int k = 0; k < np; k++) {
+            const double dpk = pf[k + 1] - pf[k];
+            b[idx3(0, j, k, nt, np)] = keep * dpk * sin(tcj) * dtj * rf[0] * rf[0] * (br[(long)j * np + k] - m);
+        }
+    }
+}
+
+/* Closed wall: A Phi = b fixes Phi up to a constant.  The reported solution is
+ * the one whose mean over the shell, weighted by the cell volumes
+ * r_i^2 dr_i sin(theta_j) dtheta_j dphi_k, is zero. */
+void orc_gauge(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, double *x)
+{
+    double num = 0.0, den = 0.0;
+    for (int i = 0; i < nr; i++) {
+        const double rci = 0.5 * (rf[i] + rf[i + 1]), dri = rf[i + 1] - rf[i];
+        for (int j = 0; j < nt; j++) {
+            const double tcj = 0.5 * (tf[j] + tf[j + 1]), dtj = tf[j + 1] - tf[j];
+            for (int k = 0; k < np; k++) {
+                const double v = rci * rci * dri * sin(tcj) * dtj * (pf[k + 1] - pf[k]);
+                num += v * x[idx3(i, j, k, nt, np)];
+                den += v;
+            }
+        }
+    }
+    const double m = num / den;
+    const long N = (long)nr * nt * np;
+    for (long P = 0; P < N; P++) x[P] -= m;
 }
 
 /* ---- compensated dot over a fixed partition (deterministic for any thread count) */
