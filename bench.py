@@ -313,6 +313,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-cache-budget", type=float, default=None,
                     help="bytes streamed per iteration by the batch (server default: 256 MiB; 0 = no limit)")
+    ap.add_argument("--no-closed-wall", action="store_true", help="skip the closed-wall solve")
     ap.add_argument("--no-refined", action="store_true", help="skip the FP32-refined solves of the default run")
     args = ap.parse_args()
     if args.summarize_pmc:
@@ -451,6 +452,21 @@ def main():
                               "status": pot3d.STATUS_NAMES.get(st2, st2), "relres_true": rr2}
         print(f"[bench] two-pass: {it2 / t2:.1f} it/s ({it2} iters)", file=sys.stderr, flush=True)
         solver.set_iteration(pot3d.ITER_ONE_SWEEP)
+    if not args.no_closed_wall:
+        # the closed-wall upper boundary (Br = 0 on R1) on the same grid and data, one solve
+        cw = Solver(*faces, upper_bc=pot3d.UPPER_CLOSED_WALL, device=0)
+        d_phi_cw = torch.empty_like(d_phi)
+        cw.solve_device(d_br, d_phi_cw, w.tol, maxit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st3, it3, rr3 = cw.solve_device(d_br, d_phi_cw, w.tol, maxit)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter() - t0
+        result["closed_wall"] = {"iters_per_s": round(it3 / t3, 2), "iters": it3, "solve_s": round(t3, 4),
+                                 "status": pot3d.STATUS_NAMES.get(st3, st3), "relres_true": rr3}
+        print(f"[bench] closed wall: {it3 / t3:.1f} it/s ({it3} iters)", file=sys.stderr, flush=True)
+        cw.close()
+        del d_phi_cw
     if not args.no_refined:
         # FP32-refined solves of the same problem to the same FP64 residual
         phi64 = d_phi.clone()

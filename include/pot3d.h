@@ -58,8 +58,12 @@ enum pot3d_status {
 
 enum pot3d_upper_bc {
     POT3D_UPPER_SOURCE_SURFACE = 0,   /* Phi(R1) = 0 (Sec. 2.1)                                   */
-    POT3D_UPPER_CLOSED_WALL = 1       /* Br(R1) = 0 (Sec. 2.1); singular system, not supported:
-                                         POT3D_EINVAL                                            */
+    POT3D_UPPER_CLOSED_WALL = 1       /* Br(R1) = 0 (Sec. 2.1): no flux through the top face.  The
+                                         system is singular (constants); the area-weighted mean of
+                                         Br (its monopole, which a closed shell cannot carry) is
+                                         removed from b, data that are a monopole up to rounding
+                                         give Phi = 0, and Phi is returned with zero mean weighted
+                                         by the cell volumes.  Single solves only (not the server). */
 };
 
 enum pot3d_refine_mode {
@@ -116,7 +120,7 @@ typedef struct pot3d_stats {
  *   t_faces[0..nt]   strictly increasing polar faces, t_faces[0] = 0, t_faces[nt] = pi
  *   p_faces[0..np]   strictly increasing azimuthal faces, p_faces[np] - p_faces[0] = 2 pi
  *   nr >= 2, nt >= 2, np >= 3.  Arrays are host memory, copied.
- *   upper_bc   POT3D_UPPER_SOURCE_SURFACE (closed wall is rejected with POT3D_EINVAL)
+ *   upper_bc   POT3D_UPPER_SOURCE_SURFACE or POT3D_UPPER_CLOSED_WALL
  *   precision  POT3D_FP64 or POT3D_FP32_REFINED
  * On success *out owns device buffers of about 40 N bytes (FP64) or 32 N + 20 N
  * bytes (FP32-refined).
@@ -164,7 +168,8 @@ int pot3d_apply_device(pot3d_ctx *ctx, const double *d_x, double *d_y, void *str
 
 /*
  * Right-hand side b (device, N): the surface flux of Br through the r = R0
- * faces on the first radial layer, zero elsewhere (eq. (2) as a boundary flux).
+ * faces on the first radial layer, zero elsewhere (eq. (2) as a boundary flux);
+ * with the closed wall, of Br less its monopole.
  */
 int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stream);
 

@@ -82,9 +82,8 @@ int validate_grid(const double *rf, int nr, const double *tf, int nt, const doub
         return fail(nullptr, POT3D_EINVAL, "phi faces must be finite and strictly increasing");
     if (std::fabs(pf[np] - pf[0] - kTwoPi) > 1e-12)
         return fail(nullptr, POT3D_EINVAL, "phi faces must span exactly 2 pi");
-    if (upper_bc == POT3D_UPPER_CLOSED_WALL)
-        return fail(nullptr, POT3D_EINVAL, "closed-wall upper boundary (singular system) is not supported");
-    if (upper_bc != POT3D_UPPER_SOURCE_SURFACE) return fail(nullptr, POT3D_EINVAL, "unknown upper_bc");
+    if (upper_bc != POT3D_UPPER_SOURCE_SURFACE && upper_bc != POT3D_UPPER_CLOSED_WALL)
+        return fail(nullptr, POT3D_EINVAL, "unknown upper_bc");
     if (precision != POT3D_FP64 && precision != POT3D_FP32_REFINED)
         return fail(nullptr, POT3D_EINVAL, "unsupported precision");
     return POT3D_OK;
@@ -110,7 +109,9 @@ void build_tables(pot3d_ctx *c)
             RowCoef &e = c->rows_h[(size_t)i * nt + j];
             e.rm = (i > 0) ? face * rf[i] * rf[i] / (rc[i] - rc[i - 1]) : 0.0;
             e.rp = (i < nr - 1) ? face * rf[i + 1] * rf[i + 1] / (rc[i + 1] - rc[i]) : 0.0;
-            const double dtop = (i == nr - 1) ? face * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]) : 0.0;
+            // the top face: Phi = 0 there (source surface), or no flux (closed wall)
+            const double dtop = (i == nr - 1 && c->upper_bc == POT3D_UPPER_SOURCE_SURFACE)
+                                    ? face * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]) : 0.0;
             // pole faces (j = 0 below, j = nt-1 above) have sin(theta) = 0: no coupling
             e.tm = (j > 0) ? dr[i] * std::sin(tf[j]) / (tc[j] - tc[j - 1]) : 0.0;
             e.tp = (j < nt - 1) ? dr[i] * std::sin(tf[j + 1]) / (tc[j + 1] - tc[j]) : 0.0;
@@ -127,6 +128,13 @@ void build_tables(pot3d_ctx *c)
     }
     c->bfac_h.resize(nt);
     for (int j = 0; j < nt; ++j) c->bfac_h[j] = std::sin(tc[j]) * dt[j] * rf[0] * rf[0];
+    c->vr_h.resize(nr);
+    c->vt_h.resize(nt);
+    double sr = 0.0, st = 0.0, sp = 0.0;
+    for (int i = 0; i < nr; ++i) sr += (c->vr_h[i] = rc[i] * rc[i] * dr[i]);
+    for (int j = 0; j < nt; ++j) st += (c->vt_h[j] = std::sin(tc[j]) * dt[j]);
+    for (int k = 0; k < np; ++k) sp += c->dphi_h[k];
+    c->inv_volume = 1.0 / (sr * st * sp);
 }
 
 // Launch shape of one stencil pass.  `tile` picks the kernel:
@@ -487,7 +495,7 @@ void free_ctx(pot3d_ctx *c)
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
-                    c->bplane, c->br, c->partial, c->poles, c->sc,
+                    c->bplane, c->br, c->partial, c->poles, c->vr, c->vt, c->bcs, c->sc,
                     c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -525,7 +533,9 @@ int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMem
     const size_t rowb = (size_t)c->np * sizeof(double), pitchb = (size_t)c->pitch * sizeof(double);
     const size_t nrows = (size_t)c->nr * c->nt;
     c->have_solution = false;
-    HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, c->bplane, s));
+    const bool closed = c->upper_bc == POT3D_UPPER_CLOSED_WALL;
+    if (closed) HIP_TRY(c, launch_monopole(br_dev, c->bfac, c->dphi, c->nt, c->np, c->bcs, s));
+    HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, closed ? c->bcs : nullptr, c->bplane, s));
     if (phi0 && kind_in == hipMemcpyHostToDevice && c->pitch != c->np) {
         // one contiguous host copy into r (free until the solve starts), then
         // the padded layout on the device
@@ -720,6 +730,9 @@ int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStrea
     tv.store_r = 0;
     tv.ignore_done = 1;
     if (fin.zero_solution) HIP_TRY(c, launch_fill<double>(c->x, c->npad, 0.0, s));
+    else if (c->upper_bc == POT3D_UPPER_CLOSED_WALL)
+        HIP_TRY(c, launch_gauge(c->x, c->vr, c->vt, c->dphi, c->nr, c->nt, c->np, c->pitch, c->inv_volume, c->partial,
+                                c->max_blocks, c->bcs + 2, s));
     HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, tv, s));
     HIP_TRY(c, launch_finish(kFinTrue, c->sc, c->partial, c->grid_o.nblocks, s));
     HIP_TRY(c, launch_poles(c->x, c->dphi, c->nr, c->nt, c->np, c->pitch, kTwoPi, c->poles, s));
@@ -964,6 +977,7 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     c->nt = nt;
     c->np = np;
     c->precision = precision;
+    c->upper_bc = upper_bc;
     // rows padded to an even length at least, so two-cell (16-byte) accesses stay in the row
     int align = std::max(2, env_int("POT3D_PITCH_ALIGN", 8));
     align += align & 1;
@@ -1021,12 +1035,18 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(dalloc(&c->br, (size_t)nt * np));
     CREATE_TRY(dalloc(&c->partial, (size_t)kMaxPartials * c->max_blocks));
     CREATE_TRY(dalloc(&c->poles, (size_t)2 * nr));
+    CREATE_TRY(dalloc(&c->vr, (size_t)nr));
+    CREATE_TRY(dalloc(&c->vt, (size_t)nt));
+    CREATE_TRY(dalloc(&c->bcs, 4));
     CREATE_TRY(dalloc(&c->sc, 1));
     CREATE_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->h_sc), 2 * sizeof(DevScalars), hipHostMallocDefault));
     CREATE_TRY(hipMemcpyAsync(c->rows, c->rows_h.data(), c->rows_h.size() * sizeof(RowCoef), hipMemcpyHostToDevice, c->stream));
     CREATE_TRY(hipMemcpyAsync(c->dphi, c->dphi_h.data(), np * sizeof(double), hipMemcpyHostToDevice, c->stream));
     CREATE_TRY(hipMemcpyAsync(c->ih, c->ih_h.data(), np * sizeof(double), hipMemcpyHostToDevice, c->stream));
     CREATE_TRY(hipMemcpyAsync(c->bfac, c->bfac_h.data(), nt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    CREATE_TRY(hipMemcpyAsync(c->vr, c->vr_h.data(), nr * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    CREATE_TRY(hipMemcpyAsync(c->vt, c->vt_h.data(), nt * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    CREATE_TRY(launch_fill<double>(c->bcs, 4, 0.0, c->stream));
     for (double *b : {c->x, c->r, c->p[0], c->p[1]}) CREATE_TRY(launch_fill<double>(b, c->npad, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->bplane, (long long)nt * c->pitch, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->poles, 2LL * nr, 0.0, c->stream));
@@ -1179,7 +1199,10 @@ int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stre
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
     hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
     const size_t rowb = (size_t)ctx->np * sizeof(double), pitchb = (size_t)ctx->pitch * sizeof(double);
-    HIP_TRY(ctx, launch_rhs(d_br, ctx->bfac, ctx->dphi, ctx->nt, ctx->np, ctx->pitch, ctx->bplane, s));
+    const bool closed = ctx->upper_bc == POT3D_UPPER_CLOSED_WALL;
+    if (closed) HIP_TRY(ctx, launch_monopole(d_br, ctx->bfac, ctx->dphi, ctx->nt, ctx->np, ctx->bcs, s));
+    HIP_TRY(ctx, launch_rhs(d_br, ctx->bfac, ctx->dphi, ctx->nt, ctx->np, ctx->pitch, closed ? ctx->bcs : nullptr,
+                            ctx->bplane, s));
     HIP_TRY(ctx, launch_fill<double>(d_b, ctx->n, 0.0, s));
     HIP_TRY(ctx, copy_rows(d_b, rowb, ctx->bplane, pitchb, rowb, (size_t)ctx->nt, hipMemcpyDeviceToDevice, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));

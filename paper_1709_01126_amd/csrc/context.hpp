@@ -31,15 +31,20 @@ struct pot3d_ctx {
     int graph_m = 16;
     GridArgs grid_p{}, grid_r{}, grid_o{};   // update-p, update-r, other passes
 
+    int upper_bc = POT3D_UPPER_SOURCE_SURFACE;
     std::vector<double> rf, tf, pf;
     std::vector<RowCoef> rows_h;
     std::vector<double> dphi_h, ih_h, bfac_h;
+    std::vector<double> vr_h, vt_h;   // cell volume factors r_i^2 dr_i and sin(theta_j) dtheta_j
+    double inv_volume = 0.0;          // 1 / shell volume as the sum of the cell volumes
 
     // device memory
     RowCoef *rows = nullptr;
     double *dphi = nullptr, *ih = nullptr, *bfac = nullptr;
     double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr};
     double *bplane = nullptr, *br = nullptr, *partial = nullptr, *poles = nullptr;
+    double *vr = nullptr, *vt = nullptr;   // closed wall: cell volume factors
+    double *bcs = nullptr;   // closed wall: [0] monopole of Br, [1] keep flag, [2] gauge mean
     DevScalars *sc = nullptr;
     DevScalars *h_sc = nullptr;     // pinned: two status slots for polling
     hipStream_t stream = nullptr;

@@ -1426,13 +1426,124 @@ dots_rz_kernel(GridArgs g, const float *r, double *partial, int nblocks)
 
 // b on the first radial layer: dphi_k * bfac_j * Br(j, k), with
 // bfac_j = sin(theta_j) dtheta_j R0^2 (the r = R0 face area over dphi_k).
+// b on the first layer; mono (closed wall only, else NULL): [0] the monopole
+// of Br to subtract, [1] 1, or 0 when the data are a monopole up to rounding.
 __global__ void rhs_kernel(const double *br, const double *bfac, const double *dphi, int nt, int np, int pitch,
-                           double *bplane)
+                           const double *mono, double *bplane)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y;
     if (j >= nt || k >= pitch) return;
-    bplane[(long long)j * pitch + k] = (k < np) ? dphi[k] * bfac[j] * br[(long long)j * np + k] : 0.0;
+    double v = 0.0;
+    if (k < np) {
+        const double b = br[(long long)j * np + k];
+        v = mono ? mono[1] * (dphi[k] * bfac[j] * (b - mono[0])) : dphi[k] * bfac[j] * b;
+    }
+    bplane[(long long)j * pitch + k] = v;
+}
+
+// Closed wall (Sec. 2.1, Br = 0 on R1): the system is singular and solvable
+// only for data without net flux.  One workgroup, fixed order: the monopole
+// of Br, its mean over r = R0 with the face areas dphi_k bfac_j as weights,
+// into out[0]; out[1] = 0 if the weighted 2-norm of Br - mean is at most
+// 1e-14 of that of Br (a monopole up to rounding: b = 0), else 1.
+__global__ void __launch_bounds__(256) monopole_kernel(const double *br, const double *bfac, const double *dphi, int nt,
+                                                       int np, double *out)
+{
+    __shared__ double sh[3][256];
+    const int t = threadIdx.x;
+    const long long n = (long long)nt * np;
+    double num = 0.0, den = 0.0, raw = 0.0;
+    for (long long q = t; q < n; q += 256) {
+        const int j = (int)(q / np), k = (int)(q % np);
+        const double w = dphi[k] * bfac[j];
+        const double v = br[q];
+        num += w * v;
+        den += w;
+        raw += (w * v) * (w * v);
+    }
+    sh[0][t] = num;
+    sh[1][t] = den;
+    sh[2][t] = raw;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st)
+            for (int c = 0; c < 3; ++c) sh[c][t] += sh[c][t + st];
+        __syncthreads();
+    }
+    const double m = sh[0][0] / sh[1][0];
+    const double raw_all = sh[2][0];
+    __syncthreads();
+    double rest = 0.0;
+    for (long long q = t; q < n; q += 256) {
+        const int j = (int)(q / np), k = (int)(q % np);
+        const double w = dphi[k] * bfac[j];
+        const double d = w * (br[q] - m);
+        rest += d * d;
+    }
+    sh[0][t] = rest;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) sh[0][t] += sh[0][t + st];
+        __syncthreads();
+    }
+    if (t == 0) {
+        out[0] = m;
+        out[1] = (sh[0][0] <= 1e-28 * raw_all) ? 0.0 : 1.0;
+    }
+}
+
+// Closed wall: Phi is fixed up to a constant; the reported solution has zero
+// mean weighted by the cell volumes vr_i vt_j dphi_k (vr = r_i^2 dr_i,
+// vt = sin(theta_j) dtheta_j).  Partial sums of the weighted Phi, one
+// workgroup per strided set of (i, j) rows in a fixed order.
+__global__ void __launch_bounds__(256) gauge_partials_kernel(const double *x, const double *vr, const double *vt,
+                                                             const double *dphi, int nr, int nt, int np, int pitch,
+                                                             double *partial, int nblocks)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    const int nrows = nr * nt;
+    for (int row = blockIdx.x; row < nrows; row += nblocks) {
+        const double w = vr[row / nt] * vt[row % nt];
+        const double *xr = x + (long long)row * pitch;
+        for (int k = t; k < np; k += 256) acc += w * dphi[k] * xr[k];
+    }
+    sh[t] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) sh[t] += sh[t + st];
+        __syncthreads();
+    }
+    if (t == 0) partial[blockIdx.x] = sh[0];
+}
+
+// mean = inv_volume * sum of the partials (one workgroup, fixed order) into *out
+__global__ void __launch_bounds__(256) gauge_mean_kernel(const double *partial, int nb, double inv_volume, double *out)
+{
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int q = t; q < nb; q += 256) acc += partial[q];
+    sh[t] = acc;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if (t < st) sh[t] += sh[t + st];
+        __syncthreads();
+    }
+    if (t == 0) *out = sh[0] * inv_volume;
+}
+
+// x -= *mean on the cells (the row padding stays zero)
+__global__ void gauge_shift_kernel(double *x, long long nrows, int np, int pitch, const double *mean)
+{
+    const double m = *mean;
+    const long long n = nrows * np;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const long long row = q / np;
+        x[row * pitch + (q - row * np)] -= m;
+    }
 }
 
 template <typename V>
@@ -1697,10 +1808,27 @@ hipError_t launch_finish(int which, DevScalars *sc, const double *partial, int n
 }
 
 hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, int nt, int np, int pitch,
-                      double *bplane, hipStream_t s)
+                      const double *mono, double *bplane, hipStream_t s)
 {
     const dim3 grid((pitch + 255) / 256, nt), block(256);
-    rhs_kernel<<<grid, block, 0, s>>>(br, bfac, dphi, nt, np, pitch, bplane);
+    rhs_kernel<<<grid, block, 0, s>>>(br, bfac, dphi, nt, np, pitch, mono, bplane);
+    return hipGetLastError();
+}
+
+hipError_t launch_monopole(const double *br, const double *bfac, const double *dphi, int nt, int np, double *out,
+                           hipStream_t s)
+{
+    monopole_kernel<<<1, 256, 0, s>>>(br, bfac, dphi, nt, np, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge(double *x, const double *vr, const double *vt, const double *dphi, int nr, int nt, int np,
+                        int pitch, double inv_volume, double *partial, int nblocks, double *mean, hipStream_t s)
+{
+    const int nb = std::max(1, std::min(nblocks, nr * nt));
+    gauge_partials_kernel<<<nb, 256, 0, s>>>(x, vr, vt, dphi, nr, nt, np, pitch, partial, nb);
+    gauge_mean_kernel<<<1, 256, 0, s>>>(partial, nb, inv_volume, mean);
+    gauge_shift_kernel<<<2048, 256, 0, s>>>(x, (long long)nr * nt, np, pitch, mean);
     return hipGetLastError();
 }
 

@@ -66,8 +66,18 @@ hipError_t launch_stencil_batch(int mode, int tile, const BatchSlot<V> *slots, i
                                 hipStream_t s);
 hipError_t launch_finish_batch(int which, const BatchFin *fins, int nslots, hipStream_t s);
 
+// b on the first layer from Br; mono: NULL, or (closed wall) the output of
+// launch_monopole, whose monopole is subtracted.
 hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, int nt, int np, int pitch,
-                      double *bplane, hipStream_t s);
+                      const double *mono, double *bplane, hipStream_t s);
+// Closed wall: out[0] = area-weighted mean of Br, out[1] = 0 if Br is that
+// mean up to rounding, else 1 (device, 2 doubles).
+hipError_t launch_monopole(const double *br, const double *bfac, const double *dphi, int nt, int np, double *out,
+                           hipStream_t s);
+// Closed wall: x -= its mean weighted by vr_i vt_j dphi_k (inv_volume = 1 / sum
+// of the weights); partial holds nblocks doubles, *mean receives the mean.
+hipError_t launch_gauge(double *x, const double *vr, const double *vt, const double *dphi, int nr, int nt, int np,
+                        int pitch, double inv_volume, double *partial, int nblocks, double *mean, hipStream_t s);
 
 template <typename V>
 hipError_t launch_fill(V *p, long long n, V val, hipStream_t s);
