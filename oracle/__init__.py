@@ -60,6 +60,8 @@ def _load():
         lib.orc_rhs_bc.restype = None
         lib.orc_gauge.argtypes = [d, i, d, i, d, i, d]
         lib.orc_gauge.restype = None
+        lib.orc_field.argtypes = [d, i, d, i, d, i, i, d, d, d, d, d]
+        lib.orc_field.restype = None
         lib.orc_matvec.argtypes = [i, i, i, d, d, d]
         lib.orc_matvec.restype = None
         lib.orc_rhs.argtypes = [d, i, d, i, d, i, d, d]
@@ -119,6 +121,25 @@ def rhs(rf, tf, pf, br, closed_wall: bool = False, return_monopole: bool = False
     else:
         _load().orc_rhs(_p(rf), nr, _p(tf), nt, _p(pf), np_, _p(br), _p(b))
     return (b, mono.value) if return_monopole else b
+
+
+def field(rf, tf, pf, x, br, closed_wall: bool = False):
+    """B = -grad Phi on the cell faces: (Br (nr+1, nt, np), Bt (nr, nt+1, np),
+    Bp (nr, nt, np) on the faces k+1/2).  br: the surface data, of which the
+    part that enters b is used on r = R0."""
+    rf, tf, pf = _f64(rf), _f64(tf), _f64(pf)
+    nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
+    b = rhs(rf, tf, pf, br, closed_wall)
+    tc = 0.5 * (tf[1:] + tf[:-1])
+    w = (np.sin(tc) * np.diff(tf))[:, None] * np.diff(pf)[None, :] * rf[0] ** 2
+    br0 = np.ascontiguousarray(b[0] / w)
+    x = _f64(x).reshape(nr, nt, np_)
+    bfr = np.empty((nr + 1, nt, np_))
+    bft = np.empty((nr, nt + 1, np_))
+    bfp = np.empty((nr, nt, np_))
+    _load().orc_field(_p(rf), nr, _p(tf), nt, _p(pf), np_, int(bool(closed_wall)), _p(br0), _p(x), _p(bfr),
+                      _p(bft), _p(bfp))
+    return bfr, bft, bfp
 
 
 def gauge(rf, tf, pf, x) -> np.ndarray:

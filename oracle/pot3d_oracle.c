@@ -252,6 +252,57 @@ void orc_gauge(const double *rf, int nr, const double *tf, int nt, const double 
     for (long P = 0; P < N; P++) x[P] -= m;
 }
 
+/* The field B = -grad Phi (Sec. 2.1; the paper's B = grad Phi with our sign of
+ * Phi) on the faces of the cells, by the same differences as the operator:
+ *   Br on r-faces, (nr+1) x nt x np: -(Phi_i - Phi_{i-1}) / (r_i - r_{i-1})
+ *      inside; the surface data br0 (Br less any removed monopole) on r = R0;
+ *      on r = R1 Phi_{nr-1} / (R1 - r_{nr-1}) (Phi = 0 on the face), or 0 with
+ *      the closed wall;
+ *   Bt on theta-faces, nr x (nt+1) x np: -(Phi_j - Phi_{j-1}) / (r_i (theta_j - theta_{j-1}))
+ *      inside, 0 on the pole faces;
+ *   Bp on phi-faces k+1/2, nr x nt x np: -(Phi_{k+1} - Phi_k) / (r_i sin(theta_j) s_k),
+ *      s_k the centre spacing (across the seam: phi_0 + 2 pi - phi_{np-1}).
+ * With the face areas rf^2 sin(theta_j) dtheta_j dphi_k, r_i dr_i sin(tf_j) dphi_k and
+ * r_i dr_i dtheta_j, the net outward flux of B from each cell is (A Phi - b) there. */
+void orc_field(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int closed_wall,
+               const double *br0, const double *x, double *bfr, double *bft, double *bfp)
+{
+    double *rc = malloc(sizeof(double) * nr), *tc = malloc(sizeof(double) * nt), *pc = malloc(sizeof(double) * np);
+    if (!rc || !tc || !pc) {
+        free(rc); free(tc); free(pc);
+        return;
+    }
+    for (int i = 0; i < nr; i++) rc[i] = 0.5 * (rf[i] + rf[i + 1]);
+    for (int j = 0; j < nt; j++) tc[j] = 0.5 * (tf[j] + tf[j + 1]);
+    for (int k = 0; k < np; k++) pc[k] = 0.5 * (pf[k] + pf[k + 1]);
+    for (int i = 0; i <= nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                double v;
+                if (i == 0) v = br0[(long)j * np + k];
+                else if (i == nr) v = closed_wall ? 0.0 : x[idx3(nr - 1, j, k, nt, np)] / (rf[nr] - rc[nr - 1]);
+                else v = -(x[idx3(i, j, k, nt, np)] - x[idx3(i - 1, j, k, nt, np)]) / (rc[i] - rc[i - 1]);
+                bfr[((long)i * nt + j) * np + k] = v;
+            }
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j <= nt; j++)
+            for (int k = 0; k < np; k++) {
+                double v = 0.0;
+                if (j > 0 && j < nt)
+                    v = -(x[idx3(i, j, k, nt, np)] - x[idx3(i, j - 1, k, nt, np)]) / (rc[i] * (tc[j] - tc[j - 1]));
+                bft[((long)i * (nt + 1) + j) * np + k] = v;
+            }
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j < nt; j++)
+            for (int k = 0; k < np; k++) {
+                const int kp = (k == np - 1) ? 0 : k + 1;
+                const double sp = (k < np - 1) ? pc[k + 1] - pc[k] : pc[0] + ORC_TWO_PI - pc[np - 1];
+                bfp[idx3(i, j, k, nt, np)] =
+                    -(x[idx3(i, j, kp, nt, np)] - x[idx3(i, j, k, nt, np)]) / (rc[i] * sin(tc[j]) * sp);
+            }
+    free(rc); free(tc); free(pc);
+}
+
 /* ---- compensated dot over a fixed partition (deterministic for any thread count) */
 #define ORC_CHUNKS 256
 
