@@ -440,6 +440,22 @@ def main():
         "relres_true": stats["relres_true"],
         "phi_l2": phi_norm,
     }
+    # the field B = -grad Phi of the solution on the cell faces (reads Phi, writes
+    # three face arrays: about 32 bytes per unknown)
+    nr_, nt_, np_ = w.nr, w.nt, w.np
+    fbr = torch.empty((nr_ + 1, nt_, np_), dtype=torch.float64, device=dev)
+    fbt = torch.empty((nr_, nt_ + 1, np_), dtype=torch.float64, device=dev)
+    fbp = torch.empty((nr_, nt_, np_), dtype=torch.float64, device=dev)
+    sptr = torch.cuda.current_stream(dev).cuda_stream
+    pot3d.pot3d_field_device(solver.ctx, fbr.data_ptr(), fbt.data_ptr(), fbp.data_ptr(), sptr)
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        rcf = pot3d.pot3d_field_device(solver.ctx, fbr.data_ptr(), fbt.data_ptr(), fbp.data_ptr(), sptr)
+    tf_ = (time.perf_counter() - t0) / reps
+    result["field"] = {"ms": round(tf_ * 1e3, 3), "status": pot3d.STATUS_NAMES.get(rcf, rcf),
+                       "gbs_alg": round((8.0 * w.n + 8.0 * (fbr.numel() + fbt.numel() + fbp.numel())) / tf_ / 1e9, 1)}
+    del fbr, fbt, fbp
     if one_sweep:
         # the two-pass form of the same FP64 iteration, one solve, for comparison
         solver.set_iteration(pot3d.ITER_TWO_PASS)

@@ -180,6 +180,22 @@ int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stre
  */
 int pot3d_pole_values(const pot3d_ctx *ctx, double *north, double *south);
 
+/*
+ * The field of the last solution, B = -grad Phi (Sec. 2.1; the paper writes
+ * B = grad Phi for the opposite sign of Phi), on the cell faces by the
+ * scheme's own differences, device buffers, phi fastest:
+ *   d_br  (nr+1)*nt*np  Br on the r-faces i = 0..nr: the surface data on R0
+ *         (less the monopole with the closed wall), Phi / half-cell on R1
+ *         (0 with the closed wall);
+ *   d_bt  nr*(nt+1)*np  Btheta on the theta-faces j = 0..nt (0 on the poles);
+ *   d_bp  nr*nt*np      Bphi on the phi-faces k+1/2 (periodic).
+ * With the face areas of the scheme, the net outward flux of B from each cell
+ * is the residual (A Phi - b) there.  Ordered on `stream` (NULL = the
+ * context's), returns when done.  POT3D_EINVAL before a solve, or after
+ * pot3d_rhs_device or pot3d_time_kernels.
+ */
+int pot3d_field_device(pot3d_ctx *ctx, double *d_br, double *d_bt, double *d_bp, void *stream);
+
 /* Statistics of the last solve. */
 int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
 

@@ -135,6 +135,15 @@ void build_tables(pot3d_ctx *c)
     for (int j = 0; j < nt; ++j) st += (c->vt_h[j] = std::sin(tc[j]) * dt[j]);
     for (int k = 0; k < np; ++k) sp += c->dphi_h[k];
     c->inv_volume = 1.0 / (sr * st * sp);
+    // field output: inverse centre spacings of the r- and theta-faces (0 where
+    // the face carries the boundary value or no field), 1 / r_i, 1 / sin(theta_j)
+    c->ftab_h.assign((size_t)(nr + 1) + (nt + 1) + nr + nt, 0.0);
+    double *fr = c->ftab_h.data(), *ft = fr + nr + 1, *rinv = ft + nt + 1, *sinv = rinv + nr;
+    for (int i = 1; i < nr; ++i) fr[i] = 1.0 / (rc[i] - rc[i - 1]);
+    fr[nr] = c->upper_bc == POT3D_UPPER_SOURCE_SURFACE ? 1.0 / (rf[nr] - rc[nr - 1]) : 0.0;
+    for (int j = 1; j < nt; ++j) ft[j] = 1.0 / (tc[j] - tc[j - 1]);
+    for (int i = 0; i < nr; ++i) rinv[i] = 1.0 / rc[i];
+    for (int j = 0; j < nt; ++j) sinv[j] = 1.0 / std::sin(tc[j]);
 }
 
 // Launch shape of one stencil pass.  `tile` picks the kernel:
@@ -495,7 +504,7 @@ void free_ctx(pot3d_ctx *c)
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
-                    c->bplane, c->br, c->partial, c->poles, c->vr, c->vt, c->bcs, c->sc,
+                    c->bplane, c->br, c->partial, c->poles, c->vr, c->vt, c->bcs, c->ftab, c->sc,
                     c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -533,6 +542,7 @@ int prepare_solve(pot3d_ctx *c, const double *br_dev, const double *phi0, hipMem
     const size_t rowb = (size_t)c->np * sizeof(double), pitchb = (size_t)c->pitch * sizeof(double);
     const size_t nrows = (size_t)c->nr * c->nt;
     c->have_solution = false;
+    c->field_ready = false;
     const bool closed = c->upper_bc == POT3D_UPPER_CLOSED_WALL;
     if (closed) HIP_TRY(c, launch_monopole(br_dev, c->bfac, c->dphi, c->nt, c->np, c->bcs, s));
     HIP_TRY(c, launch_rhs(br_dev, c->bfac, c->dphi, c->nt, c->np, c->pitch, closed ? c->bcs : nullptr, c->bplane, s));
@@ -767,6 +777,7 @@ int finish_solve(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStrea
     if (const unsigned line = take_oob_line(s))
         return fail(c, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
     c->have_solution = true;
+    c->field_ready = true;
     if (iters) *iters = total_iters;
     if (relres_true) *relres_true = st.relres_true;
     if (fin.status == POT3D_EBREAKDOWN) return fail(c, POT3D_EBREAKDOWN, "breakdown: non-finite data or p.Ap <= 0");
@@ -1038,6 +1049,7 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(dalloc(&c->vr, (size_t)nr));
     CREATE_TRY(dalloc(&c->vt, (size_t)nt));
     CREATE_TRY(dalloc(&c->bcs, 4));
+    CREATE_TRY(dalloc(&c->ftab, c->ftab_h.size()));
     CREATE_TRY(dalloc(&c->sc, 1));
     CREATE_TRY(hipHostMalloc(reinterpret_cast<void **>(&c->h_sc), 2 * sizeof(DevScalars), hipHostMallocDefault));
     CREATE_TRY(hipMemcpyAsync(c->rows, c->rows_h.data(), c->rows_h.size() * sizeof(RowCoef), hipMemcpyHostToDevice, c->stream));
@@ -1047,6 +1059,8 @@ int create_context(const double *r_faces, int nr, const double *t_faces, int nt,
     CREATE_TRY(hipMemcpyAsync(c->vr, c->vr_h.data(), nr * sizeof(double), hipMemcpyHostToDevice, c->stream));
     CREATE_TRY(hipMemcpyAsync(c->vt, c->vt_h.data(), nt * sizeof(double), hipMemcpyHostToDevice, c->stream));
     CREATE_TRY(launch_fill<double>(c->bcs, 4, 0.0, c->stream));
+    CREATE_TRY(hipMemcpyAsync(c->ftab, c->ftab_h.data(), c->ftab_h.size() * sizeof(double), hipMemcpyHostToDevice,
+                              c->stream));
     for (double *b : {c->x, c->r, c->p[0], c->p[1]}) CREATE_TRY(launch_fill<double>(b, c->npad, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->bplane, (long long)nt * c->pitch, 0.0, c->stream));
     CREATE_TRY(launch_fill<double>(c->poles, 2LL * nr, 0.0, c->stream));
@@ -1200,11 +1214,27 @@ int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stre
     hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
     const size_t rowb = (size_t)ctx->np * sizeof(double), pitchb = (size_t)ctx->pitch * sizeof(double);
     const bool closed = ctx->upper_bc == POT3D_UPPER_CLOSED_WALL;
+    ctx->field_ready = false;   // the b plane no longer holds the last solve's
     if (closed) HIP_TRY(ctx, launch_monopole(d_br, ctx->bfac, ctx->dphi, ctx->nt, ctx->np, ctx->bcs, s));
     HIP_TRY(ctx, launch_rhs(d_br, ctx->bfac, ctx->dphi, ctx->nt, ctx->np, ctx->pitch, closed ? ctx->bcs : nullptr,
                             ctx->bplane, s));
     HIP_TRY(ctx, launch_fill<double>(d_b, ctx->n, 0.0, s));
     HIP_TRY(ctx, copy_rows(d_b, rowb, ctx->bplane, pitchb, rowb, (size_t)ctx->nt, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    return POT3D_OK;
+}
+
+int pot3d_field_device(pot3d_ctx *ctx, double *d_br, double *d_bt, double *d_bp, void *stream)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (!d_br || !d_bt || !d_bp) return fail(ctx, POT3D_EINVAL, "output pointers are required");
+    if (!ctx->field_ready) return fail(ctx, POT3D_EINVAL, "no solution to take the field of (solve first)");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
+    const double *fr = ctx->ftab, *ft = fr + ctx->nr + 1, *rinv = ft + ctx->nt + 1, *sinv = rinv + ctx->nr;
+    HIP_TRY(ctx, launch_field(ctx->x, ctx->bplane, ctx->bfac, ctx->dphi, ctx->ih, fr, ft, rinv, sinv, ctx->nr, ctx->nt,
+                              ctx->np, ctx->pitch, d_br, d_bt, d_bp, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     return POT3D_OK;
 }
@@ -1256,6 +1286,7 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
         rc = time_pair<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p, ms_update_r);
     }
     ctx->have_solution = false;
+    ctx->field_ready = false;
     if (rc == POT3D_OK) {
         if (const unsigned line = take_oob_line(ctx->stream))
             return fail(ctx, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));

@@ -44,6 +44,8 @@ struct pot3d_ctx {
     double *x = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr};
     double *bplane = nullptr, *br = nullptr, *partial = nullptr, *poles = nullptr;
     double *vr = nullptr, *vt = nullptr;   // closed wall: cell volume factors
+    double *ftab = nullptr;   // field output: fr (nr+1), ft (nt+1), 1/r_i (nr), 1/sin(theta_j) (nt)
+    std::vector<double> ftab_h;
     double *bcs = nullptr;   // closed wall: [0] monopole of Br, [1] keep flag, [2] gauge mean
     DevScalars *sc = nullptr;
     DevScalars *h_sc = nullptr;     // pinned: two status slots for polling
@@ -72,6 +74,7 @@ struct pot3d_ctx {
 
     bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;
+    bool field_ready = false;     // x and the b plane belong to the last solve
     pot3d_stats stats{};
     std::string err;
 };

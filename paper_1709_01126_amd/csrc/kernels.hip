@@ -1535,6 +1535,51 @@ __global__ void __launch_bounds__(256) gauge_mean_kernel(const double *partial, 
     if (t == 0) *out = sh[0] * inv_volume;
 }
 
+// The field B = -grad Phi on the cell faces (Sec. 2.1; output layouts
+// unpadded, phi fastest), by the operator's differences:
+//   Br (nr+1) x nt x np:  r = R0 the surface data (b / (dphi_k bfac_j) on the
+//      first layer), inside -(Phi_i - Phi_{i-1}) fr_i, r = R1 Phi_{nr-1} fr_nr
+//      (fr_nr = 0 with the closed wall);
+//   Bt nr x (nt+1) x np:  -(Phi_j - Phi_{j-1}) ft_j / r_i (ft = 0 on the poles);
+//   Bp nr x nt x np (faces k+1/2):  -(Phi_{k+1} - Phi_k) ih_k / (r_i sin(theta_j)).
+// fr, ft: inverse centre spacings; rinv = 1 / r_i; sinv = 1 / sin(theta_j).
+__global__ void field_kernel(const double *x, const double *bplane, const double *bfac, const double *dphi,
+                             const double *ih, const double *fr, const double *ft, const double *rinv,
+                             const double *sinv, int nr, int nt, int np, int pitch, double *bfr, double *bft,
+                             double *bfp)
+{
+    const long long nrr = (long long)(nr + 1) * nt * np, ntt = (long long)nr * (nt + 1) * np;
+    const long long npp = (long long)nr * nt * np;
+    const long long total = nrr + ntt + npp;
+    auto X = [&](int i, int j, int k) { return x[((long long)i * nt + j) * pitch + k]; };
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+         q += (long long)gridDim.x * blockDim.x) {
+        if (q < nrr) {
+            const int k = (int)(q % np);
+            const long long ij = q / np;
+            const int j = (int)(ij % nt), i = (int)(ij / nt);
+            double v;
+            if (i == 0) v = bplane[(long long)j * pitch + k] / (dphi[k] * bfac[j]);
+            else if (i == nr) v = X(nr - 1, j, k) * fr[nr];
+            else v = -(X(i, j, k) - X(i - 1, j, k)) * fr[i];
+            bfr[q] = v;
+        } else if (q < nrr + ntt) {
+            const long long u = q - nrr;
+            const int k = (int)(u % np);
+            const long long ij = u / np;
+            const int j = (int)(ij % (nt + 1)), i = (int)(ij / (nt + 1));
+            bft[u] = (j == 0 || j == nt) ? 0.0 : -(X(i, j, k) - X(i, j - 1, k)) * ft[j] * rinv[i];
+        } else {
+            const long long u = q - nrr - ntt;
+            const int k = (int)(u % np);
+            const long long ij = u / np;
+            const int j = (int)(ij % nt), i = (int)(ij / nt);
+            const int kp = (k == np - 1) ? 0 : k + 1;
+            bfp[u] = -(X(i, j, kp) - X(i, j, k)) * ih[k] * rinv[i] * sinv[j];
+        }
+    }
+}
+
 // x -= *mean on the cells (the row padding stays zero)
 __global__ void gauge_shift_kernel(double *x, long long nrows, int np, int pitch, const double *mean)
 {
@@ -1812,6 +1857,14 @@ hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, 
 {
     const dim3 grid((pitch + 255) / 256, nt), block(256);
     rhs_kernel<<<grid, block, 0, s>>>(br, bfac, dphi, nt, np, pitch, mono, bplane);
+    return hipGetLastError();
+}
+
+hipError_t launch_field(const double *x, const double *bplane, const double *bfac, const double *dphi, const double *ih,
+                        const double *fr, const double *ft, const double *rinv, const double *sinv, int nr, int nt,
+                        int np, int pitch, double *bfr, double *bft, double *bfp, hipStream_t s)
+{
+    field_kernel<<<4096, 256, 0, s>>>(x, bplane, bfac, dphi, ih, fr, ft, rinv, sinv, nr, nt, np, pitch, bfr, bft, bfp);
     return hipGetLastError();
 }
 

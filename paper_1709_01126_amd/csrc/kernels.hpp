@@ -74,6 +74,10 @@ hipError_t launch_rhs(const double *br, const double *bfac, const double *dphi, 
 // mean up to rounding, else 1 (device, 2 doubles).
 hipError_t launch_monopole(const double *br, const double *bfac, const double *dphi, int nt, int np, double *out,
                            hipStream_t s);
+// B = -grad Phi on the cell faces from x (padded) and the b plane (device).
+hipError_t launch_field(const double *x, const double *bplane, const double *bfac, const double *dphi, const double *ih,
+                        const double *fr, const double *ft, const double *rinv, const double *sinv, int nr, int nt,
+                        int np, int pitch, double *bfr, double *bft, double *bfp, hipStream_t s);
 // Closed wall: x -= its mean weighted by vr_i vt_j dphi_k (inv_volume = 1 / sum
 // of the weights); partial holds nblocks doubles, *mean receives the mean.
 hipError_t launch_gauge(double *x, const double *vr, const double *vt, const double *dphi, int nr, int nt, int np,

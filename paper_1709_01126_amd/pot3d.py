@@ -25,7 +25,7 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
                 EBREAKDOWN: "EBREAKDOWN"}
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
-            "pot3d_pole_values", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
+            "pot3d_pole_values", "pot3d_field_device", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
             "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
@@ -109,6 +109,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_set_refinement_mode.restype = i
     lib.pot3d_set_iteration.argtypes = [vp, i]
     lib.pot3d_set_iteration.restype = i
+    lib.pot3d_field_device.argtypes = [vp, vp, vp, vp, vp]
+    lib.pot3d_field_device.restype = i
     lib.pot3d_destroy.argtypes = [vp]
     lib.pot3d_destroy.restype = None
     lib.pot3d_last_error.argtypes = [vp]
@@ -230,6 +232,10 @@ def pot3d_set_iteration(ctx, iteration):
     return load().pot3d_set_iteration(ctx, int(iteration))
 
 
+def pot3d_field_device(ctx, d_br, d_bt, d_bp, stream=None):
+    return load().pot3d_field_device(ctx, d_br, d_bt, d_bp, stream)
+
+
 def pot3d_destroy(ctx):
     if ctx:
         load().pot3d_destroy(ctx)
@@ -314,6 +320,21 @@ class Solver:
 
     def set_iteration(self, iteration):
         self._check(pot3d_set_iteration(self.ctx, iteration), (OK,))
+
+    def field(self, stream=None):
+        """B = -grad Phi of the last solution on the cell faces, as torch CUDA
+        tensors (Br (nr+1, nt, np), Btheta (nr, nt+1, np), Bphi (nr, nt, np))."""
+        import torch
+
+        nr, nt, np_ = self.shape
+        dev = torch.device("cuda", torch.cuda.current_device())
+        br = torch.empty((nr + 1, nt, np_), dtype=torch.float64, device=dev)
+        bt = torch.empty((nr, nt + 1, np_), dtype=torch.float64, device=dev)
+        bp = torch.empty((nr, nt, np_), dtype=torch.float64, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        self._check(pot3d_field_device(self.ctx, br.data_ptr(), bt.data_ptr(), bp.data_ptr(), stream.cuda_stream), (OK,))
+        return br, bt, bp
 
     def close(self):
         if self.ctx:

@@ -119,6 +119,7 @@ def test_null_arguments():
     assert P.pot3d_time_kernels(None, 3)[0] == P.EINVAL
     assert P.pot3d_set_refinement_mode(None, P.REFINE_RELIABLE) == P.EINVAL
     assert P.pot3d_set_iteration(None, P.ITER_ONE_SWEEP) == P.EINVAL
+    assert P.pot3d_field_device(None, 1, 2, 3) == P.EINVAL
     P.pot3d_destroy(None)
 
 
