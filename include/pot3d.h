@@ -271,15 +271,18 @@ const char *pot3d_version(void);
  *      memory fits the budget, and the bytes that the active solves stream
  *      per iteration stay within the cache budget (or no solve is active);
  *   3. advances every active solve by a fixed number of PCG iterations
- *      (16), all in one replay of one captured HIP graph.
+ *      (32 sweeps in the one-sweep form, 16 two-pass iterations otherwise;
+ *      the form is POT3D_ITERATION's when the server is created, one sweep
+ *      by default), all in one replay of one captured HIP graph.
  * As in Sec. 3.1, the vectors of a solve stay in device memory from
  * admission to retirement.  Device memory per grid (tables and vectors) is
  * cached and reused by later requests on the same grid.  A solve that has
  * converged stops iterating at once, while the others go on.  Every result
  * is bitwise the one pot3d_solve gives for the same request on a context of
- * the same precision with the default launch shape, for grids whose vectors
- * are below 512 MiB (above that, pot3d_solve switches to a shape for
- * HBM-streaming grids, which the server does not use).
+ * the same precision, iteration form and the default launch shape, for grids
+ * whose vectors are below 512 MiB (above that, pot3d_solve switches to a
+ * shape for HBM-streaming grids, which the server does not use).  Requests
+ * take the source-surface upper boundary.
  * ------------------------------------------------------------------------ */
 typedef struct pot3d_server pot3d_server;
 
