@@ -1543,39 +1543,55 @@ __global__ void __launch_bounds__(256) gauge_mean_kernel(const double *partial, 
 //   Bt nr x (nt+1) x np:  -(Phi_j - Phi_{j-1}) ft_j / r_i (ft = 0 on the poles);
 //   Bp nr x nt x np (faces k+1/2):  -(Phi_{k+1} - Phi_k) ih_k / (r_i sin(theta_j)).
 // fr, ft: inverse centre spacings; rinv = 1 / r_i; sinv = 1 / sin(theta_j).
-__global__ void field_kernel(const double *x, const double *bplane, const double *bfac, const double *dphi,
-                             const double *ih, const double *fr, const double *ft, const double *rinv,
-                             const double *sinv, int nr, int nt, int np, int pitch, double *bfr, double *bft,
-                             double *bfp)
+// One workgroup per output row (a phi row of one component); the row decode
+// is uniform and the lanes stream along phi.
+__global__ void __launch_bounds__(256) field_kernel(const double *x, const double *bplane, const double *bfac,
+                                                    const double *dphi, const double *ih, const double *fr,
+                                                    const double *ft, const double *rinv, const double *sinv, int nr,
+                                                    int nt, int np, int pitch, double *bfr, double *bft, double *bfp)
 {
-    const long long nrr = (long long)(nr + 1) * nt * np, ntt = (long long)nr * (nt + 1) * np;
-    const long long npp = (long long)nr * nt * np;
-    const long long total = nrr + ntt + npp;
-    auto X = [&](int i, int j, int k) { return x[((long long)i * nt + j) * pitch + k]; };
-    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < total;
-         q += (long long)gridDim.x * blockDim.x) {
-        if (q < nrr) {
-            const int k = (int)(q % np);
-            const long long ij = q / np;
-            const int j = (int)(ij % nt), i = (int)(ij / nt);
-            double v;
-            if (i == 0) v = bplane[(long long)j * pitch + k] / (dphi[k] * bfac[j]);
-            else if (i == nr) v = X(nr - 1, j, k) * fr[nr];
-            else v = -(X(i, j, k) - X(i - 1, j, k)) * fr[i];
-            bfr[q] = v;
-        } else if (q < nrr + ntt) {
-            const long long u = q - nrr;
-            const int k = (int)(u % np);
-            const long long ij = u / np;
-            const int j = (int)(ij % (nt + 1)), i = (int)(ij / (nt + 1));
-            bft[u] = (j == 0 || j == nt) ? 0.0 : -(X(i, j, k) - X(i, j - 1, k)) * ft[j] * rinv[i];
+    const long long rows_r = (long long)(nr + 1) * nt, rows_t = (long long)nr * (nt + 1);
+    const long long rows = rows_r + rows_t + (long long)nr * nt;
+    const int t = threadIdx.x;
+    auto xrow = [&](int i, int j) { return x + ((long long)i * nt + j) * pitch; };
+    for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
+        if (row < rows_r) {
+            const int i = (int)(row / nt), j = (int)(row % nt);
+            double *out = bfr + row * np;
+            if (i == 0) {
+                const double *bp = bplane + (long long)j * pitch;
+                const double bj = bfac[j];
+                for (int k = t; k < np; k += 256) out[k] = bp[k] / (dphi[k] * bj);
+            } else if (i == nr) {
+                const double *xa = xrow(nr - 1, j);
+                const double f = fr[nr];
+                for (int k = t; k < np; k += 256) out[k] = xa[k] * f;
+            } else {
+                const double *xa = xrow(i, j), *xb = xrow(i - 1, j);
+                const double f = fr[i];
+                for (int k = t; k < np; k += 256) out[k] = -(xa[k] - xb[k]) * f;
+            }
+        } else if (row < rows_r + rows_t) {
+            const long long u = row - rows_r;
+            const int i = (int)(u / (nt + 1)), j = (int)(u % (nt + 1));
+            double *out = bft + u * np;
+            if (j == 0 || j == nt) {
+                for (int k = t; k < np; k += 256) out[k] = 0.0;
+            } else {
+                const double *xa = xrow(i, j), *xb = xrow(i, j - 1);
+                const double f = ft[j] * rinv[i];
+                for (int k = t; k < np; k += 256) out[k] = -(xa[k] - xb[k]) * f;
+            }
         } else {
-            const long long u = q - nrr - ntt;
-            const int k = (int)(u % np);
-            const long long ij = u / np;
-            const int j = (int)(ij % nt), i = (int)(ij / nt);
-            const int kp = (k == np - 1) ? 0 : k + 1;
-            bfp[u] = -(X(i, j, kp) - X(i, j, k)) * ih[k] * rinv[i] * sinv[j];
+            const long long u = row - rows_r - rows_t;
+            const int i = (int)(u / nt), j = (int)(u % nt);
+            double *out = bfp + u * np;
+            const double *xa = xrow(i, j);
+            const double f = rinv[i] * sinv[j];
+            for (int k = t; k < np; k += 256) {
+                const int kp = (k == np - 1) ? 0 : k + 1;
+                out[k] = -(xa[kp] - xa[k]) * ih[k] * f;
+            }
         }
     }
 }
@@ -1864,7 +1880,9 @@ hipError_t launch_field(const double *x, const double *bplane, const double *bfa
                         const double *fr, const double *ft, const double *rinv, const double *sinv, int nr, int nt,
                         int np, int pitch, double *bfr, double *bft, double *bfp, hipStream_t s)
 {
-    field_kernel<<<4096, 256, 0, s>>>(x, bplane, bfac, dphi, ih, fr, ft, rinv, sinv, nr, nt, np, pitch, bfr, bft, bfp);
+    const long long rows = (long long)(nr + 1) * nt + (long long)nr * (nt + 1) + (long long)nr * nt;
+    const unsigned grid = (unsigned)std::min<long long>(rows, 1LL << 20);
+    field_kernel<<<grid, 256, 0, s>>>(x, bplane, bfac, dphi, ih, fr, ft, rinv, sinv, nr, nt, np, pitch, bfr, bft, bfp);
     return hipGetLastError();
 }
 
