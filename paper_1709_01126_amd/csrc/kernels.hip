@@ -807,11 +807,12 @@ stencil_wave_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 // holds box rows [wR, wR + R).  For each layer a of the chunk, and one layer
 // beyond each end:
 //   stage A, layer a, on the box less its outer ring: A p_{j-1}, r_j, z_j,
-//     p_j (theta neighbours of p_{j-1} from an LDS plane, radial ones from
-//     registers);
-//   stage B, layer a - 1, interior: w_j = A p_j and the dot products (theta
-//     neighbours of p_j from a second LDS plane).
-// Each plane has three LDS slots in rotation: one barrier per layer.
+//     p_j (p_{j-1} of layers a-1, a, a+1 from LDS planes);
+//   stage B, layer a - 1, interior: w_j = A p_j and the dot products (p_j of
+//     layers a-2, a-1 from LDS planes, of layer a from registers).
+// Each vector has three LDS layer slots in rotation: one barrier per layer.
+// The row coefficients of three layers are staged in LDS too, and r, x and
+// p_{j-1} of the next layers are loaded one layer ahead.
 // ---------------------------------------------------------------------------
 // Reciprocal of a positive normal value: the hardware estimate refined by
 // two Newton steps y <- y + y (1 - d y), each of which squares the relative
@@ -907,10 +908,7 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     // last cell (their values are never used).
     int kk = (k0 - 2 + min(lane, tkn + 3)) % np;
     if (kk < 0) kk += np;
-    const unsigned kboff = (unsigned)kk * (unsigned)sizeof(V);
-    (void)kboff;
     const bool col_in = lane >= 2 && lane < tkn + 2;    // interior cell
-    const bool col_a = lane >= 1 && lane < tkn + 3;     // stage-A cell
     const V dph = (V)gdphi[CHK(kk, np)];
     const V ihm = (V)gih[CHK(kk == 0 ? np - 1 : kk - 1, np)];
     const V ihk = (V)gih[CHK(kk, np)];
