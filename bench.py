@@ -321,7 +321,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this solver runs on a single device (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md but not built.", file=sys.stderr)
+              "a decomposition over several GPUs (radial slabs with a halo exchange per sweep) is not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.serve:
