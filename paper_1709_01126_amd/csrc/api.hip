@@ -187,14 +187,17 @@ GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed = 0)
 // lines) over radial chunks of ci layers.  Every workgroup walks its chunk
 // from start to end, so the launch runs fastest as a single wave of
 // workgroups that fills as many of the `target` resident slots as possible:
-// the rule takes the tile height (down to 4 rows below the maximum) and the
-// chunk count (chunks of at least 16 layers) with the most workgroups up to
-// `target`, preferring taller tiles.  Measured at 151 x 301 x 601 (768
-// slots): 11-row tiles in 2 chunks, 728 workgroups, 299 us per sweep against
-// 314 us for 12-row tiles (676 workgroups) and 348 us for 11-row tiles in 3
-// chunks (1092).  A grid with more tiles than slots takes the tallest tiles
-// and whole-radius chunks.  POT3D_SWEEP_TJ, POT3D_SWEEP_TK and POT3D_SWEEP_CI
-// override.
+// the rule takes the tile height (FP64: down to 4 rows below the maximum;
+// FP32: the maximum) and the chunk count (chunks of at least 16 layers) with
+// the most workgroups up to `target`, preferring taller tiles.  Measured at
+// 151 x 301 x 601: FP64 (768 slots), 11-row tiles in 2 chunks, 728
+// workgroups, 299 us per sweep against 314 us for 12-row tiles (676
+// workgroups) and 348 us for 11-row tiles in 3 chunks (1092); FP32 (1280
+// slots, which hide latency better, so the ring of shorter tiles costs more
+// than empty slots), 12-row tiles in 3 chunks, 1014 workgroups, 182 us
+// against 194 us for 10-row tiles (1209).  A grid with more tiles than slots
+// takes the tallest tiles and whole-radius chunks.  POT3D_SWEEP_TJ,
+// POT3D_SWEEP_TK and POT3D_SWEEP_CI override.
 GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target)
 {
     const int tjmax = 4 * rows - 4;
@@ -207,7 +210,8 @@ GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target)
     if (tj_env <= 0 || ci_env <= 0) {
         long long best = 0;
         const int min_ci = std::min(c->nr, 16);
-        for (int t = tjmax; t >= std::max(1, tjmax - 4); --t) {
+        const int lowest = c->precision == POT3D_FP32_REFINED ? tjmax : std::max(1, tjmax - 4);
+        for (int t = tjmax; t >= lowest; --t) {
             if (tj_env > 0 && t != tj_env) continue;
             const long long tiles = (long long)((c->nt + t - 1) / t) * ntk;
             for (int nch = 1; nch <= c->nr; ++nch) {
