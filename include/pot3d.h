@@ -282,7 +282,8 @@ const char *pot3d_version(void);
  * the same precision, iteration form and the default launch shape, for grids
  * whose vectors are below 512 MiB (above that, pot3d_solve switches to a
  * shape for HBM-streaming grids, which the server does not use).  Requests
- * take the source-surface upper boundary.
+ * take the source-surface upper boundary.  In the one-sweep form a request
+ * whose grid needs vectors of 4 GiB or more finishes with POT3D_EINVAL.
  * ------------------------------------------------------------------------ */
 typedef struct pot3d_server pot3d_server;
 
