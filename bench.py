@@ -438,7 +438,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3),
         "higher_is_better": True,
-        "scaling": "weak",
+        "scaling": None,   # one GPU: no scaling claim
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",

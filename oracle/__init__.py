@@ -27,6 +27,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pot3d_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# Mutation testing only: a copy of the oracle compiled with a planted mistake
+# (tests/test_oracle_mutations.py) is loaded from this path instead.
+_LIB_OVERRIDE = os.environ.get("POT3D_ORACLE_LIB")
 
 OK, EINVAL, ENOMEM, ENOCONV, EBREAKDOWN = 0, -1, -2, -4, -5
 NCOEF = 8
@@ -48,8 +51,11 @@ def build(force: bool = False) -> str:
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build()
+            lib = ctypes.CDLL(_LIB)
         d = ctypes.POINTER(ctypes.c_double)
         i = ctypes.c_int
         lib.orc_assemble.argtypes = [d, i, d, i, d, i, d]
@@ -71,6 +77,11 @@ def _load():
         lib.orc_pcg.argtypes = [i, i, i, d, d, d, ctypes.c_double, i,
                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
         lib.orc_pcg.restype = i
+        lib.orc_pcg_pc.argtypes = [i, i, i, d, d, d, ctypes.c_double, i, i,
+                                   ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)]
+        lib.orc_pcg_pc.restype = i
+        lib.orc_line_solve.argtypes = [i, i, i, d, d, d]
+        lib.orc_line_solve.restype = i
         lib.orc_true_relres.argtypes = [i, i, i, d, d, d]
         lib.orc_true_relres.restype = ctypes.c_double
         lib.orc_pole_values.argtypes = [i, i, i, d, d, d, d]
@@ -155,16 +166,32 @@ def dot(a: np.ndarray, b: np.ndarray) -> float:
     return float(_load().orc_dot(_p(a), _p(b), a.size))
 
 
-def pcg(coef: np.ndarray, b: np.ndarray, tol: float, maxit: int, x0=None):
-    """Jacobi-PCG.  Returns (x, iters, relres_recursive, status)."""
+PRECONDITIONERS = {"jacobi": 0, "phi_line": 1}
+
+
+def pcg(coef: np.ndarray, b: np.ndarray, tol: float, maxit: int, x0=None, precond: str = "jacobi"):
+    """PCG with the point-Jacobi ("jacobi", PC1 of Sec. 2.3) or the phi-line
+    block preconditioner ("phi_line").  Returns (x, iters, relres_recursive, status)."""
     _, nr, nt, np_ = coef.shape
     b = _f64(b).reshape(nr, nt, np_)
     x = np.zeros_like(b) if x0 is None else _f64(x0).reshape(nr, nt, np_).copy()
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
-    st = _load().orc_pcg(nr, nt, np_, _p(coef), _p(b), _p(x), float(tol), int(maxit),
-                         ctypes.byref(it), ctypes.byref(rr))
+    st = _load().orc_pcg_pc(nr, nt, np_, _p(coef), _p(b), _p(x), float(tol), int(maxit), PRECONDITIONERS[precond],
+                            ctypes.byref(it), ctypes.byref(rr))
     return x, it.value, rr.value, st
+
+
+def line_solve(coef: np.ndarray, r: np.ndarray) -> np.ndarray:
+    """z = M^-1 r for the phi-line block preconditioner (one periodic
+    tridiagonal solve per (i, j) row)."""
+    _, nr, nt, np_ = coef.shape
+    r = _f64(r).reshape(nr, nt, np_)
+    z = np.empty_like(r)
+    st = _load().orc_line_solve(nr, nt, np_, _p(coef), _p(r), _p(z))
+    if st != OK:
+        raise RuntimeError(f"orc_line_solve failed: {st}")
+    return z
 
 
 def true_relres(coef: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:
@@ -183,13 +210,13 @@ def pole_values(pf, x: np.ndarray):
     return n, s
 
 
-def solve(rf, tf, pf, br, tol: float, maxit: int, x0=None, closed_wall: bool = False):
+def solve(rf, tf, pf, br, tol: float, maxit: int, x0=None, closed_wall: bool = False, precond: str = "jacobi"):
     """Assemble, form b and run PCG.  Returns dict with phi, iters, relres, true_relres, status.
     closed_wall: Br = 0 on r = R1; the monopole of Br is removed from b and
     the solution is returned with zero cell-volume-weighted mean."""
     coef = assemble(rf, tf, pf, closed_wall)
     b = rhs(rf, tf, pf, br, closed_wall)
-    x, iters, relres, st = pcg(coef, b, tol, maxit, x0)
+    x, iters, relres, st = pcg(coef, b, tol, maxit, x0, precond)
     if closed_wall:
         x = gauge(rf, tf, pf, x)
     return {"phi": x, "iters": iters, "relres": relres, "status": st,

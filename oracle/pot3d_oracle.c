@@ -334,6 +334,96 @@ double orc_dot(const double *a, const double *b, long n)
 }
 
 /* ---------------------------------------------------------------------------
+ * phi-line Jacobi: a block preconditioner whose blocks are whole azimuthal
+ * rows.  Sec. 2.3 uses the diagonal of A (PC1); its closing remarks (Sec. 6)
+ * ask for other preconditioners that vectorize well.  Near the poles the
+ * azimuthal weights (which carry 1 / sin(theta)) dwarf the radial and polar
+ * ones, and the point-Jacobi diagonal cannot represent that coupling.
+ *
+ * M keeps, for every (i, j) row, the diagonal of A and its two azimuthal
+ * neighbour weights (periodic in phi) and drops every coupling between rows.
+ * Each block is symmetric and strictly diagonally dominant (the diagonal also
+ * holds the radial and polar weights, and every cell has a radial
+ * neighbour), so M is SPD and M^-1 exists.
+ *
+ * z = M^-1 r is one periodic tridiagonal solve per row.  For a row of n >= 3
+ * cells with diagonal d_k, lower weight a_k = W_phi-(k) and upper weight
+ * c_k = W_phi+(k):
+ *     d_k z_k - a_k z_{k-1} - c_k z_{k+1} = r_k      (indices mod n)
+ * The two corner entries (-a_0 in row 0, -c_{n-1} in row n-1) are split off
+ * as a rank-one term u v^T with u = (g, 0, .., 0, -c_{n-1}),
+ * v = (1, 0, .., 0, -a_0 / g) and g = -d_0, leaving a tridiagonal T whose
+ * first and last diagonal entries are d_0 - g and d_{n-1} - c_{n-1} a_0 / g.
+ * The Sherman-Morrison formula then gives
+ *     z = y - (v.y / (1 + v.q)) q,   T y = r,   T q = u,
+ * and both solves with T are plain Thomas eliminations sharing one forward
+ * sweep.  n = 1 has no azimuthal coupling (z = r / d); for n = 2 both
+ * neighbours are the other cell and the 2 x 2 block is solved directly.
+ * ------------------------------------------------------------------------- */
+int orc_line_solve(int nr, int nt, int np, const double *coef, const double *r, double *z)
+{
+    const long N = (long)nr * nt * np;
+    const double *D = coef + C_DIAG * N, *WPM = coef + C_PM * N, *WPP = coef + C_PP * N;
+    const long rows = (long)nr * nt;
+    int status = ORC_OK;
+    #pragma omp parallel
+    {
+        double *cp = malloc(sizeof(double) * (np > 0 ? np : 1));
+        double *y = malloc(sizeof(double) * (np > 0 ? np : 1));
+        double *q = malloc(sizeof(double) * (np > 0 ? np : 1));
+        if (!cp || !y || !q) {
+            #pragma omp atomic write
+            status = ORC_ENOMEM;
+        }
+        #pragma omp for schedule(static)
+        for (long row = 0; row < rows; row++) {
+            if (!cp || !y || !q) continue;
+            const long o = row * np;
+            const double *d = D + o, *a = WPM + o, *c = WPP + o, *rr = r + o;
+            double *zz = z + o;
+            if (np == 1) {
+                zz[0] = rr[0] / d[0];
+                continue;
+            }
+            if (np == 2) {
+                const double m01 = -(a[0] + c[0]), m10 = -(a[1] + c[1]);
+                const double det = d[0] * d[1] - m01 * m10;
+                zz[0] = (d[1] * rr[0] - m01 * rr[1]) / det;
+                zz[1] = (d[0] * rr[1] - m10 * rr[0]) / det;
+                continue;
+            }
+            const int n = np;
+            const double g = -d[0];
+            /* forward sweep of T for both right-hand sides r and u */
+            double w = d[0] - g;
+            cp[0] = -c[0] / w;
+            y[0] = rr[0] / w;
+            q[0] = g / w;
+            for (int k = 1; k < n; k++) {
+                double dk = d[k];
+                if (k == n - 1) dk -= c[n - 1] * a[0] / g;
+                const double lk = -a[k];
+                w = dk - lk * cp[k - 1];
+                cp[k] = (k < n - 1) ? -c[k] / w : 0.0;
+                const double uk = (k == n - 1) ? -c[n - 1] : 0.0;
+                y[k] = (rr[k] - lk * y[k - 1]) / w;
+                q[k] = (uk - lk * q[k - 1]) / w;
+            }
+            for (int k = n - 2; k >= 0; k--) {
+                y[k] -= cp[k] * y[k + 1];
+                q[k] -= cp[k] * q[k + 1];
+            }
+            const double vy = y[0] - (a[0] / g) * y[n - 1];
+            const double vq = q[0] - (a[0] / g) * q[n - 1];
+            const double f = vy / (1.0 + vq);
+            for (int k = 0; k < n; k++) zz[k] = y[k] - f * q[k];
+        }
+        free(cp); free(y); free(q);
+    }
+    return status;
+}
+
+/* ---------------------------------------------------------------------------
  * Jacobi-preconditioned CG (Sec. 2.3; Saad, Algorithm 9.1 with M = diag(A)).
  *
  *   x = x0; r = b - A x; z = r / d; p = z; rho = r.z
@@ -348,11 +438,35 @@ double orc_dot(const double *a, const double *b, long n)
  * iters = 0.  Non-finite data give ORC_EBREAKDOWN with the last finite
  * iterate.  tol = 0 runs exactly maxit iterations (fixed-count mode).
  * ------------------------------------------------------------------------- */
+/* The preconditioner of orc_pcg_pc: the diagonal of A (PC1, Sec. 2.3), or the
+ * phi-line blocks of orc_line_solve. */
+#define ORC_PC_JACOBI 0
+#define ORC_PC_PHI_LINE 1
+
+static int precondition(int precond, int nr, int nt, int np, const double *coef, const double *r, double *z)
+{
+    const long N = (long)nr * nt * np;
+    if (precond == ORC_PC_PHI_LINE) return orc_line_solve(nr, nt, np, coef, r, z);
+    const double *D = coef + C_DIAG * N;
+    #pragma omp parallel for schedule(static)
+    for (long P = 0; P < N; P++) z[P] = r[P] / D[P];
+    return ORC_OK;
+}
+
+int orc_pcg_pc(int nr, int nt, int np, const double *coef, const double *b, double *x,
+               double tol, int maxit, int precond, int *iters_out, double *relres_out);
+
 int orc_pcg(int nr, int nt, int np, const double *coef, const double *b, double *x,
             double tol, int maxit, int *iters_out, double *relres_out)
 {
+    return orc_pcg_pc(nr, nt, np, coef, b, x, tol, maxit, ORC_PC_JACOBI, iters_out, relres_out);
+}
+
+/* The same PCG with z = M^-1 r from the chosen preconditioner. */
+int orc_pcg_pc(int nr, int nt, int np, const double *coef, const double *b, double *x,
+               double tol, int maxit, int precond, int *iters_out, double *relres_out)
+{
     const long N = (long)nr * nt * np;
-    const double *D = coef + C_DIAG * N;
     double *r = malloc(sizeof(double) * N), *z = malloc(sizeof(double) * N);
     double *p = malloc(sizeof(double) * N), *q = malloc(sizeof(double) * N);
     int status = ORC_OK, iters = 0;
@@ -372,8 +486,9 @@ int orc_pcg(int nr, int nt, int np, const double *coef, const double *b, double 
     if (!isfinite(relres)) { status = ORC_EBREAKDOWN; goto done; }
     if (relres <= tol) goto done;
 
+    if (precondition(precond, nr, nt, np, coef, r, z) != ORC_OK) { status = ORC_ENOMEM; goto done; }
     #pragma omp parallel for schedule(static)
-    for (long P = 0; P < N; P++) { z[P] = r[P] / D[P]; p[P] = z[P]; }
+    for (long P = 0; P < N; P++) p[P] = z[P];
     double rho = orc_dot(r, z, N);
 
     status = ORC_ENOCONV;
@@ -388,8 +503,7 @@ int orc_pcg(int nr, int nt, int np, const double *coef, const double *b, double 
         relres = sqrt(orc_dot(r, r, N)) / nb;
         if (!isfinite(relres)) { status = ORC_EBREAKDOWN; break; }
         if (relres <= tol) { status = ORC_OK; break; }
-        #pragma omp parallel for schedule(static)
-        for (long P = 0; P < N; P++) z[P] = r[P] / D[P];
+        if (precondition(precond, nr, nt, np, coef, r, z) != ORC_OK) { status = ORC_ENOMEM; break; }
         const double rho_new = orc_dot(r, z, N);
         const double beta = rho_new / rho;
         rho = rho_new;

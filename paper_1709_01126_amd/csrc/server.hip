@@ -769,7 +769,7 @@ int pot3d_server_get_stats(const pot3d_server *sv, pot3d_server_stats *out)
     out->queued = (int)sv->queue.size();
     out->cached_contexts = (int)sv->idle.size();
     out->max_slots = sv->max_slots;
-    out->graph_iters = sv->graph_m;
+    out->graph_iters = sv->sweep ? 2 * sv->graph_m : sv->graph_m;   // sweeps replay 2m iterations
     out->used_bytes = (double)sv->used;
     out->budget_bytes = (double)sv->budget;
     return POT3D_OK;

@@ -141,12 +141,62 @@ def load(path: str = LIB_PATH):
 def _dp(a):
     if a is None:
         return None
-    assert a.dtype == np.float64 and a.flags.c_contiguous
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous):
+        raise ValueError("expected a C-contiguous float64 numpy array")
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
 def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# Grid shape (nr, nt, np) and device of every live context, so that host
+# arrays can be checked against it before the C library reads or writes them.
+_CTX_SHAPE = {}
+
+
+def _host_in(a, n, name):
+    """A host input array as C-contiguous float64 of exactly n elements (None stays None)."""
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"{name}: {a.size} elements, the grid needs {n}")
+    return a
+
+
+def _host_out(a, n, name):
+    """A caller's output array: must already be C-contiguous float64 with n elements."""
+    if not (isinstance(a, np.ndarray) and a.dtype == np.float64 and a.flags.c_contiguous and a.flags.writeable):
+        raise ValueError(f"{name}: expected a writeable C-contiguous float64 numpy array")
+    if a.size != n:
+        raise ValueError(f"{name}: {a.size} elements, the grid needs {n}")
+    return a
+
+
+def _dev_tensor(t, n, device, name):
+    """A torch tensor handed to the library as a device pointer: float64,
+    contiguous, on the context's GPU, with exactly n elements."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor")
+    if not t.is_cuda or t.device.index != device:
+        raise ValueError(f"{name}: tensor on {t.device}, the context is on cuda:{device}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected torch.float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {n}")
+    return t
+
+
+def _shape(ctx):
+    try:
+        return _CTX_SHAPE[ctx]
+    except KeyError:
+        raise ValueError("unknown or destroyed context handle") from None
 
 
 class Pot3dError(RuntimeError):
@@ -169,13 +219,18 @@ def pot3d_create(r_faces, t_faces, p_faces, upper_bc=UPPER_SOURCE_SURFACE, preci
     out = ctypes.c_void_p(None)
     st = load().pot3d_create(_dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1,
                              int(upper_bc), int(precision), int(device), ctypes.byref(out))
+    if st == OK:
+        _CTX_SHAPE[out.value] = (rf.size - 1, tf.size - 1, pf.size - 1, int(device))
     return st, (out.value if st == OK else None)
 
 
 def pot3d_solve(ctx, br, tol, maxit, phi0, phi_out):
-    """Host solve.  phi_out: preallocated float64 array of N.  Returns (status, iters, relres_true)."""
-    br = _f64(br)
-    phi0 = _f64(phi0)
+    """Host solve.  phi_out: preallocated float64 array of N.  Returns (status, iters, relres_true).
+    Raises ValueError, before any C call, if an array does not have the grid's size."""
+    nr, nt, np_, _ = _shape(ctx)
+    br = _host_in(br, nt * np_, "br")
+    phi0 = _host_in(phi0, nr * nt * np_, "phi0")
+    _host_out(phi_out, nr * nt * np_, "phi")
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
     st = load().pot3d_solve(ctx, _dp(br), float(tol), int(maxit), _dp(phi0), _dp(phi_out), ctypes.byref(it),
@@ -184,7 +239,9 @@ def pot3d_solve(ctx, br, tol, maxit, phi0, phi_out):
 
 
 def pot3d_solve_device(ctx, d_br, d_phi0, d_phi, stream, tol, maxit):
-    """Device solve on device pointers (ints).  Returns (status, iters, relres_true)."""
+    """Device solve on raw device pointers (ints), as in C: the caller
+    guarantees nt*np and N elements (Solver.solve_device checks tensors).
+    Returns (status, iters, relres_true)."""
     it = ctypes.c_int(0)
     rr = ctypes.c_double(0.0)
     st = load().pot3d_solve_device(ctx, d_br, d_phi0, d_phi, stream, float(tol), int(maxit), ctypes.byref(it),
@@ -201,6 +258,8 @@ def pot3d_rhs_device(ctx, d_br, d_b, stream=None):
 
 
 def pot3d_pole_values(ctx, nr):
+    if nr != _shape(ctx)[0]:
+        raise ValueError(f"nr = {nr}, the context has {_shape(ctx)[0]} radial cells")
     north = np.empty(nr)
     south = np.empty(nr)
     st = load().pot3d_pole_values(ctx, _dp(north), _dp(south))
@@ -238,6 +297,7 @@ def pot3d_field_device(ctx, d_br, d_bt, d_bp, stream=None):
 
 def pot3d_destroy(ctx):
     if ctx:
+        _CTX_SHAPE.pop(ctx, None)
         load().pot3d_destroy(ctx)
 
 
@@ -251,6 +311,7 @@ class Solver:
             raise Pot3dError(st, pot3d_last_error(None))
         self.ctx = ctx
         self.nr, self.nt, self.np = len(r_faces) - 1, len(t_faces) - 1, len(p_faces) - 1
+        self.device = int(device)
         if iteration is not None:
             self.set_iteration(iteration)
 
@@ -274,10 +335,13 @@ class Solver:
         """torch CUDA float64 tensors in/out on the given (or current) stream."""
         import torch
 
+        n = self.nr * self.nt * self.np
+        _dev_tensor(br, self.nt * self.np, self.device, "br")
+        _dev_tensor(phi, n, self.device, "phi")
+        if phi0 is not None:
+            _dev_tensor(phi0, n, self.device, "phi0")
         if stream is None:
             stream = torch.cuda.current_stream(br.device)
-        for t in (br, phi) + ((phi0,) if phi0 is not None else ()):
-            assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
         st, it, rr = pot3d_solve_device(self.ctx, br.data_ptr(), phi0.data_ptr() if phi0 is not None else None,
                                         phi.data_ptr(), stream.cuda_stream, tol, maxit)
         self._check(st)
@@ -286,6 +350,11 @@ class Solver:
     def apply(self, x, y, stream=None):
         import torch
 
+        n = self.nr * self.nt * self.np
+        _dev_tensor(x, n, self.device, "x")
+        _dev_tensor(y, n, self.device, "y")
+        if x.data_ptr() == y.data_ptr():
+            raise ValueError("x and y must be distinct buffers")
         if stream is None:
             stream = torch.cuda.current_stream(x.device)
         self._check(pot3d_apply_device(self.ctx, x.data_ptr(), y.data_ptr(), stream.cuda_stream), (OK,))
@@ -293,6 +362,8 @@ class Solver:
     def rhs(self, br, b, stream=None):
         import torch
 
+        _dev_tensor(br, self.nt * self.np, self.device, "br")
+        _dev_tensor(b, self.nr * self.nt * self.np, self.device, "b")
         if stream is None:
             stream = torch.cuda.current_stream(br.device)
         self._check(pot3d_rhs_device(self.ctx, br.data_ptr(), b.data_ptr(), stream.cuda_stream), (OK,))
@@ -369,7 +440,11 @@ def pot3d_server_create(device=0, precision=FP64, max_slots=8, hbm_budget_bytes=
 def pot3d_server_submit(sv, r_faces, t_faces, p_faces, br, tol, maxit, phi_out=None):
     """phi_out: None, or a float64 array of N that receives Phi at retirement
     (keep it alive until the request is done).  Returns (status, request id)."""
-    rf, tf, pf, br = _f64(r_faces), _f64(t_faces), _f64(p_faces), _f64(br)
+    rf, tf, pf = _f64(r_faces), _f64(t_faces), _f64(p_faces)
+    nr, nt, np_ = rf.size - 1, tf.size - 1, pf.size - 1
+    br = _host_in(br, nt * np_, "br")
+    if phi_out is not None:
+        _host_out(phi_out, nr * nt * np_, "phi_out")
     rid = ctypes.c_longlong(0)
     st = load().pot3d_server_submit(sv, _dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1, _dp(br),
                                     float(tol), int(maxit), _dp(phi_out), ctypes.byref(rid))
@@ -384,8 +459,13 @@ def pot3d_server_step(sv):
 
 
 def pot3d_server_result(sv, rid, phi_out=None):
-    """phi_out: None (query only) or a float64 array of N.  Returns (status, info dict)."""
+    """phi_out: None (query only) or a float64 array of the request's N.  Returns (status, info dict)."""
     info = pot3d_request_info()
+    if phi_out is not None:
+        st = load().pot3d_server_result(sv, int(rid), None, ctypes.byref(info))
+        if st != OK:
+            return st, info.as_dict()
+        _host_out(phi_out, info.nr * info.nt * info.np, "phi_out")
     st = load().pot3d_server_result(sv, int(rid), _dp(phi_out), ctypes.byref(info))
     return st, info.as_dict()
 

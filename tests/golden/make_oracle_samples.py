@@ -39,7 +39,23 @@ def sample_indices(nr, nt, np_, count=1024, seed=2024):
     return np.array(sorted(idx), dtype=np.int64)
 
 
-def main(name, solve=True):
+def layer_functionals(x, seed=7):
+    """Per radial layer: the 2-norm, the plain sum and the dot product with a
+    seeded N(0, 1) vector of Phi.  An error confined to a region the sampled
+    indices miss still moves these to first order."""
+    nr = x.shape[0]
+    rng = np.random.default_rng(seed)
+    l2, s1, sv = [], [], []
+    for i in range(nr):
+        xi = np.ascontiguousarray(x[i]).ravel()
+        v = rng.standard_normal(xi.size)
+        l2.append(float(np.sqrt(oracle.dot(xi, xi))))
+        s1.append(float(xi.sum()))
+        sv.append(float(oracle.dot(xi, v)))
+    return {"seed": seed, "l2": l2, "sum": s1, "dot_randn": sv}
+
+
+def main(name, solve=True, save_phi=None):
     w = WORKLOADS[name]
     rf, tf, pf = w.faces()
     br = w.br((rf, tf, pf))
@@ -65,6 +81,8 @@ def main(name, solve=True):
         return
     x, iters, relres, st = oracle.pcg(coef, b, w.tol, 200_000)
     t2 = time.time()
+    if save_phi:
+        np.save(save_phi, x)
     north, south = oracle.pole_values(pf, x)
     out = {
         "_source": "oracle/pot3d_oracle.c Jacobi-PCG on the named seeded workload; written by "
@@ -76,6 +94,7 @@ def main(name, solve=True):
         "indices": idx.tolist(), "phi": x.ravel()[idx].tolist(),
         "fixed": fixed,
         "north": north.tolist(), "south": south.tolist(),
+        "layers": layer_functionals(x),
         "oracle_seconds": {"fixed_k": t1 - t0, "solve": t2 - t1},
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")
@@ -85,5 +104,7 @@ def main(name, solve=True):
 
 
 if __name__ == "__main__":
-    # python tests/golden/make_oracle_samples.py NAME [--fixed-only]
-    main(sys.argv[1] if len(sys.argv) > 1 else "bipole_151x301x601", solve="--fixed-only" not in sys.argv)
+    # python tests/golden/make_oracle_samples.py NAME [--fixed-only] [--save-phi PATH.npy]
+    sp = sys.argv[sys.argv.index("--save-phi") + 1] if "--save-phi" in sys.argv else None
+    main(sys.argv[1] if len(sys.argv) > 1 else "bipole_151x301x601", solve="--fixed-only" not in sys.argv,
+         save_phi=sp)

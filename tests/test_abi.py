@@ -110,11 +110,12 @@ def test_null_arguments():
     assert lib.pot3d_create(P._dp(rf), 4, P._dp(tf), 6, P._dp(pf), 8, 0, 0, 0, None) == P.EINVAL
     phi = np.empty(4 * 6 * 8)
     br = np.zeros(6 * 8)
-    assert P.pot3d_solve(None, br, 1e-10, 10, None, phi)[0] == P.EINVAL
+    assert lib.pot3d_solve(None, P._dp(br), 1e-10, 10, None, P._dp(phi), None, None) == P.EINVAL
     assert P.pot3d_solve_device(None, 1, None, 1, None, 1e-10, 10)[0] == P.EINVAL
     assert P.pot3d_apply_device(None, 1, 2) == P.EINVAL
     assert P.pot3d_rhs_device(None, 1, 2) == P.EINVAL
-    assert P.pot3d_pole_values(None, 4)[0] == P.EINVAL
+    north, south = np.empty(4), np.empty(4)
+    assert lib.pot3d_pole_values(None, P._dp(north), P._dp(south)) == P.EINVAL
     assert P.pot3d_get_stats(None)[0] == P.EINVAL
     assert P.pot3d_time_kernels(None, 3)[0] == P.EINVAL
     assert P.pot3d_set_refinement_mode(None, P.REFINE_RELIABLE) == P.EINVAL
@@ -150,3 +151,80 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert res.returncode == 2
     assert "one GPU" in res.stderr or "single device" in res.stderr
+
+
+# ---------------------------------------------------------------------------
+# The Python marshalling checks sizes, dtypes, layout and device before any C
+# call: the library reads nt*np or N doubles through the pointers it is given,
+# so a wrong array must never reach it.
+
+FAKE_CTX = 0x7E57   # never dereferenced: every call below must raise first
+
+
+@pytest.fixture
+def fake_ctx():
+    P._CTX_SHAPE[FAKE_CTX] = (4, 6, 8, 0)
+    yield FAKE_CTX
+    P._CTX_SHAPE.pop(FAKE_CTX, None)
+
+
+def test_host_solve_rejects_wrong_sizes(fake_ctx):
+    n = 4 * 6 * 8
+    good_br, phi = np.zeros(6 * 8), np.empty(n)
+    with pytest.raises(ValueError, match="br"):
+        P.pot3d_solve(fake_ctx, np.zeros(6 * 8 - 1), 1e-10, 10, None, phi)
+    with pytest.raises(ValueError, match="phi0"):
+        P.pot3d_solve(fake_ctx, good_br, 1e-10, 10, np.zeros(n + 1), phi)
+    with pytest.raises(ValueError, match="phi"):
+        P.pot3d_solve(fake_ctx, good_br, 1e-10, 10, None, np.empty(n - 1))
+    with pytest.raises(ValueError, match="phi"):
+        P.pot3d_solve(fake_ctx, good_br, 1e-10, 10, None, np.empty(n, dtype=np.float32))
+    with pytest.raises(ValueError, match="phi"):
+        P.pot3d_solve(fake_ctx, good_br, 1e-10, 10, None, np.empty((2 * n,))[::2])
+    with pytest.raises(ValueError, match="radial"):
+        P.pot3d_pole_values(fake_ctx, 5)
+
+
+def test_unknown_context_is_rejected():
+    with pytest.raises(ValueError, match="context"):
+        P.pot3d_solve(0x1234, np.zeros(48), 1e-10, 10, None, np.empty(192))
+
+
+def test_solver_methods_reject_bad_tensors():
+    torch = pytest.importorskip("torch")
+    s = object.__new__(P.Solver)   # no context: the checks come first
+    s.ctx, s.nr, s.nt, s.np, s.device = None, 4, 6, 8, 0
+    cpu = torch.zeros(4 * 6 * 8, dtype=torch.float64)
+    with pytest.raises(ValueError, match="cuda"):
+        s.solve_device(torch.zeros(48, dtype=torch.float64), cpu, 1e-10, 10)
+    with pytest.raises(ValueError, match="cuda"):
+        s.apply(cpu, cpu)
+    with pytest.raises(ValueError, match="cuda"):
+        s.rhs(torch.zeros(48, dtype=torch.float64), cpu)
+    with pytest.raises(ValueError, match="tensor"):
+        s.apply(np.zeros(192), cpu)
+
+
+def test_tensor_check_order_and_messages():
+    """The tensor check itself, on CPU tensors pretending to be on a device:
+    dtype, layout and element count are each rejected."""
+    torch = pytest.importorskip("torch")
+
+    class OnDevice:
+        """A CPU tensor reported as cuda:0 (the check reads is_cuda/device)."""
+        def __init__(self, t):
+            self.t = t
+
+    t = torch.zeros(10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="cuda"):
+        P._dev_tensor(t, 10, 0, "x")
+    with pytest.raises(ValueError, match="torch tensor"):
+        P._dev_tensor(OnDevice(t), 10, 0, "x")
+
+
+def test_server_submit_rejects_wrong_sizes():
+    rf, tf, pf = good_faces()
+    with pytest.raises(ValueError, match="br"):
+        P.pot3d_server_submit(None, rf, tf, pf, np.zeros(5), 1e-9, 100)
+    with pytest.raises(ValueError, match="phi_out"):
+        P.pot3d_server_submit(None, rf, tf, pf, np.zeros(6 * 8), 1e-9, 100, np.empty(3))

@@ -299,6 +299,35 @@ def _golden(name):
     return json.load(open(path))
 
 
+def check_layer_functionals(phi, g, rel):
+    """The whole solution against the oracle's in the 2-norm, through
+    functionals the golden file stores per radial layer i: ||Phi_i||, sum(Phi_i)
+    and Phi_i . v_i for seeded N(0, 1) vectors v_i.  If ||Phi - Phi_orc|| <=
+    rel ||Phi_orc||, then sqrt(sum_i d_i^2) <= rel ||Phi_orc|| for each of
+        d_i = ||Phi_i|| - ||Phi_orc,i||,
+        d_i = (sum(Phi_i) - sum(Phi_orc,i)) / sqrt(nt np),
+        d_i = (Phi_i - Phi_orc,i) . v_i / ||v_i||
+    (Cauchy-Schwarz per layer), so each is a necessary condition of the 2-norm
+    bar that an error anywhere in the grid, sampled or not, enters at first order."""
+    lay = g["layers"]
+    nr = phi.shape[0]
+    rng = np.random.default_rng(lay["seed"])
+    d_l2, d_sum, d_dot = [], [], []
+    for i in range(nr):
+        xi = np.ascontiguousarray(phi[i]).ravel()
+        v = rng.standard_normal(xi.size)
+        d_l2.append(np.linalg.norm(xi) - lay["l2"][i])
+        d_sum.append((xi.sum() - lay["sum"][i]) / math.sqrt(xi.size))
+        d_dot.append((xi @ v - lay["dot_randn"][i]) / np.linalg.norm(v))
+    bar = rel * g["phi_l2"]
+    got = {name: float(np.linalg.norm(d)) for name, d in (("l2", d_l2), ("sum", d_sum), ("dot", d_dot))}
+    print(f"[full size] layer functionals vs oracle (bar {bar:.3e}): {got}", flush=True)
+    for name, val in got.items():
+        assert val <= bar, (name, val, bar)
+    l2 = float(np.linalg.norm(phi.ravel()))
+    assert abs(l2 - g["phi_l2"]) <= rel * g["phi_l2"], (l2, g["phi_l2"])
+
+
 def test_full_size_bipole_151x301x601():
     """Full-size workload as the benchmark runs it, against sampled oracle
     values written by tests/golden/make_oracle_samples.py.  These must match:
@@ -329,6 +358,7 @@ def test_full_size_bipole_151x301x601():
     assert iters_close(it, g["iters"]), (it, g["iters"])
     err = np.abs(phi.ravel()[idx] - np.array(g["phi"])).max() / g["phi_max_abs"]
     assert err <= 1e-8, err
+    check_layer_functionals(phi, g, 1e-8)
     np.testing.assert_allclose(north, g["north"], rtol=0, atol=1e-8 * g["phi_max_abs"])
     np.testing.assert_allclose(south, g["south"], rtol=0, atol=1e-8 * g["phi_max_abs"])
     coef = oracle.assemble(rf, tf, pf)

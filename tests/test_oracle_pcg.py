@@ -149,3 +149,39 @@ def test_equatorial_antisymmetry_of_solution():
     res = oracle.solve(rf, tf, pf, br, 1e-13, 10_000)
     phi = res["phi"]
     np.testing.assert_allclose(phi[:, ::-1, :], -phi, atol=1e-11 * np.abs(phi).max())
+
+
+@pytest.mark.parametrize("case", TINY)
+def test_true_relres_fixed_values(case):
+    """The true relative residual ||b - A x||_2 / ||b||_2 (Sec. 4.1's relative
+    tolerance, recomputed from x) at points where its value is fixed by the
+    algebra alone, with x* = A^-1 b from a dense LAPACK solve:
+      x = 0        -> exactly 1 (the residual is b);
+      x = 2 x*     -> 1 (the residual is -b);
+      x = -x*      -> 2 (the residual is 2 b);
+      x = (1+e) x* -> e (the residual is -e b);
+      x = x*       -> rounding only.
+    A dropped square root, a ||b||^2 denominator or a sign error in b - A x
+    each fails one of these."""
+    _, _, _, _, coef, b = tiny_problem(case, seed=3)
+    A = oracle.to_sparse(coef).toarray()
+    xs = np.linalg.solve(A, b.ravel()).reshape(b.shape)
+    assert oracle.true_relres(coef, b, np.zeros_like(b)) == 1.0
+    assert abs(oracle.true_relres(coef, b, 2.0 * xs) - 1.0) <= 1e-12
+    assert abs(oracle.true_relres(coef, b, -xs) - 2.0) <= 1e-12
+    for eps in (1e-3, 0.25, 3.0):
+        assert abs(oracle.true_relres(coef, b, (1.0 + eps) * xs) - eps) <= 1e-9 * eps + 1e-13
+    assert oracle.true_relres(coef, b, xs) <= 1e-13
+    # a scaled problem: the ratio does not depend on the units of b
+    assert abs(oracle.true_relres(coef, 1e6 * b, 1e6 * 1.5 * xs) - 0.5) <= 1e-12
+
+
+def test_true_relres_random_against_numpy():
+    """On a random x the value equals the definition computed with numpy from
+    the dense operator (a plain sum of squares, no compensation)."""
+    _, _, _, _, coef, b = tiny_problem(TINY[-1], seed=4)
+    A = oracle.to_sparse(coef).toarray()
+    x = np.random.default_rng(5).standard_normal(b.shape)
+    res = b.ravel() - A @ x.ravel()
+    want = math.sqrt(float(res @ res)) / math.sqrt(float(b.ravel() @ b.ravel()))
+    assert abs(oracle.true_relres(coef, b, x) - want) <= 1e-13 * want
