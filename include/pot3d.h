@@ -83,6 +83,17 @@ enum pot3d_iteration {
                                   same PCG in exact arithmetic.  Default.                   */
 };
 
+enum pot3d_preconditioner {
+    POT3D_PC_JACOBI = 0,     /* point Jacobi, M = diag(A): "PC1" of Sec. 2.3 (default)       */
+    POT3D_PC_PHI_LINE = 1    /* phi-line blocks: M keeps, for every (r, theta) row, the
+                                diagonal of A and its two periodic azimuthal weights and
+                                drops the couplings between rows; z = M^-1 r is one
+                                periodic tridiagonal solve per row.  A stronger
+                                preconditioner of the kind Sec. 6 calls for: near the poles
+                                the azimuthal weights, which carry 1 / sin(theta), dominate
+                                the diagonal, and point Jacobi cannot represent them.       */
+};
+
 enum pot3d_precision {
     POT3D_FP64 = 0,          /* FP64 vectors, stencil and reductions throughout              */
     POT3D_FP32_REFINED = 1   /* FP32 inner PCG inside FP64 defect correction (see
@@ -100,8 +111,9 @@ typedef struct pot3d_stats {
     double solve_ms;         /* wall time of the last solve call on the device             */
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 48 N (FP64, one
-                                sweep), 64 N (FP64, two passes), 24 N / 32 N (FP32 inner,
-                                one sweep / two passes)                                    */
+                                sweep), 64 N (FP64, two passes), 80 N (FP64, phi-line
+                                preconditioner), 24 N / 32 N (FP32 inner, one sweep / two
+                                passes)                                                    */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -112,6 +124,8 @@ typedef struct pot3d_stats {
     int iteration;           /* POT3D_ITER_* of the iterations (FP32 inner ones if refined) */
     int sweep_rows;          /* one-sweep kernel: tile box rows per wavefront (4, 6 or 8)   */
     int chunk_s, blocks_s;   /* one-sweep kernel: radial layers per chunk, workgroups      */
+    int precond;             /* POT3D_PC_* of the last solve                               */
+    int blocks_l;            /* workgroups of the phi-line pass (0 unless POT3D_PC_PHI_LINE)*/
 } pot3d_stats;
 
 /*
@@ -165,6 +179,15 @@ int pot3d_solve_device(pot3d_ctx *ctx, const double *d_br, const double *d_phi0,
  * (NULL = the context's stream); returns after the kernel has completed.
  */
 int pot3d_apply_device(pot3d_ctx *ctx, const double *d_x, double *d_y, void *stream);
+
+/*
+ * z = M^-1 r with the context's preconditioner (pot3d_set_preconditioner:
+ * point Jacobi, the diagonal of A, Sec. 2.3; or the phi-line blocks).
+ * d_r, d_z: device, N each, phi-fastest, distinct.  FP64 contexts only
+ * (POT3D_EINVAL otherwise).  Ordered on `stream` (NULL = the context's);
+ * returns after the kernel has completed.
+ */
+int pot3d_precondition_device(pot3d_ctx *ctx, const double *d_r, double *d_z, void *stream);
 
 /*
  * Right-hand side b (device, N): the surface flux of Br through the r = R0
@@ -249,6 +272,25 @@ int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
  * POT3D_ITER_TWO_PASS only.  POT3D_EINVAL otherwise.
  */
 int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
+
+/*
+ * Preconditioner of the context's FP64 solves (Sec. 2.3 uses point Jacobi;
+ * Sec. 6 asks for stronger ones that still suit vector hardware):
+ *   POT3D_PC_JACOBI    point Jacobi (default), either iteration form;
+ *   POT3D_PC_PHI_LINE  phi-line blocks.  Each PCG iteration then runs the
+ *                      direction update on z = M^-1 r, the r/x update, and a
+ *                      line pass that solves the rows (one wavefront per row:
+ *                      the circulant block of a uniform phi grid factors
+ *                      into two first-order periodic recurrences) and writes
+ *                      z: 80 bytes per unknown per iteration against 48 or 64
+ *                      for point Jacobi, for fewer iterations.  Allocates one
+ *                      more vector (8 N bytes) on first use.
+ * POT3D_EINVAL (nothing changed) unless ctx is an FP64 context whose phi
+ * faces are uniform (every width 2 pi / np to 1e-12 relative) with
+ * np <= 2048, or for another value of pc.  POT3D_ENOMEM / POT3D_EDEVICE if
+ * the vector or the iteration graph cannot be made.
+ */
+int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc);
 
 /* Free the context and all of its device memory.  NULL is a no-op. */
 void pot3d_destroy(pot3d_ctx *ctx);

@@ -82,6 +82,8 @@ def _load():
         lib.orc_pcg_pc.restype = i
         lib.orc_line_solve.argtypes = [i, i, i, d, d, d]
         lib.orc_line_solve.restype = i
+        lib.orc_set_threads.argtypes = [i]
+        lib.orc_set_threads.restype = i
         lib.orc_true_relres.argtypes = [i, i, i, d, d, d]
         lib.orc_true_relres.restype = ctypes.c_double
         lib.orc_pole_values.argtypes = [i, i, i, d, d, d, d]
@@ -192,6 +194,12 @@ def line_solve(coef: np.ndarray, r: np.ndarray) -> np.ndarray:
     if st != OK:
         raise RuntimeError(f"orc_line_solve failed: {st}")
     return z
+
+
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads for the following oracle calls (n <= 0: unchanged);
+    returns the count in force."""
+    return int(_load().orc_set_threads(int(n)))
 
 
 def true_relres(coef: np.ndarray, b: np.ndarray, x: np.ndarray) -> float:

@@ -44,6 +44,7 @@
  * partition of the index range, so results do not depend on the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -548,4 +549,13 @@ void orc_pole_values(int nr, int nt, int np, const double *pf, const double *x, 
         north[i] = sn / span;
         south[i] = ss / span;
     }
+}
+
+/* OpenMP threads of the following calls (timing runs of the benchmark's CPU
+ * baseline: one thread as in the paper's serial baseline, Sec. 4.1, or all);
+ * returns the number the runtime will use. */
+int orc_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

@@ -7,4 +7,5 @@ kernels are in ``csrc/`` and its interface is in ``include/pot3d.h``.
 buffers and streams.
 """
 from .pot3d import (EBREAKDOWN, EDEVICE, EINVAL, ENOCONV, ENOMEM, FP32_REFINED, FP64, ITER_ONE_SWEEP,  # noqa: F401
+                    PC_JACOBI, PC_PHI_LINE,
                     ITER_TWO_PASS, OK, REFINE_RELIABLE, REFINE_RESTART, UPPER_CLOSED_WALL, UPPER_SOURCE_SURFACE, Pot3dError, Server, Solver, load)

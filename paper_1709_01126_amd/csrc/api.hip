@@ -92,49 +92,62 @@ int validate_grid(const double *rf, int nr, const double *tf, int nt, const doub
 // Separable metric tables of the volume-scaled operator (Sec. 2.2 scheme with
 // the spherical metric restored).  Cell centres are face midpoints; the top
 // face Phi = 0 couples through a half-cell difference onto the diagonal.
-void build_tables(pot3d_ctx *c)
+// Writes rows (nr * nt), dphi, ih (np), bfac (nt), vr (nr), vt (nt) and
+// 1 / (shell volume); work holds 2 nr + 2 nt + np doubles.  Allocates nothing.
+void fill_tables(int nr, int nt, int np, const double *rf, const double *tf, const double *pf, int upper_bc,
+                 RowCoef *rows, double *dphi, double *ih, double *bfac, double *vr, double *vt, double *inv_volume,
+                 double *work)
 {
-    const int nr = c->nr, nt = c->nt, np = c->np;
-    const double *rf = c->rf.data(), *tf = c->tf.data(), *pf = c->pf.data();
-    std::vector<double> rc(nr), dr(nr), tc(nt), dt(nt), pc(np);
+    double *rc = work, *dr = rc + nr, *tc = dr + nr, *dt = tc + nt, *pc = dt + nt;
     for (int i = 0; i < nr; ++i) { rc[i] = 0.5 * (rf[i] + rf[i + 1]); dr[i] = rf[i + 1] - rf[i]; }
     for (int j = 0; j < nt; ++j) { tc[j] = 0.5 * (tf[j] + tf[j + 1]); dt[j] = tf[j + 1] - tf[j]; }
     for (int k = 0; k < np; ++k) pc[k] = 0.5 * (pf[k] + pf[k + 1]);
 
-    c->rows_h.assign((size_t)nr * nt, RowCoef{});
     for (int i = 0; i < nr; ++i) {
         for (int j = 0; j < nt; ++j) {
             const double sj = std::sin(tc[j]);
             const double face = sj * dt[j];   // r-face area / (r^2 dphi)
-            RowCoef &e = c->rows_h[(size_t)i * nt + j];
+            RowCoef e{};
             e.rm = (i > 0) ? face * rf[i] * rf[i] / (rc[i] - rc[i - 1]) : 0.0;
             e.rp = (i < nr - 1) ? face * rf[i + 1] * rf[i + 1] / (rc[i + 1] - rc[i]) : 0.0;
             // the top face: Phi = 0 there (source surface), or no flux (closed wall)
-            const double dtop = (i == nr - 1 && c->upper_bc == POT3D_UPPER_SOURCE_SURFACE)
+            const double dtop = (i == nr - 1 && upper_bc == POT3D_UPPER_SOURCE_SURFACE)
                                     ? face * rf[nr] * rf[nr] / (rf[nr] - rc[nr - 1]) : 0.0;
             // pole faces (j = 0 below, j = nt-1 above) have sin(theta) = 0: no coupling
             e.tm = (j > 0) ? dr[i] * std::sin(tf[j]) / (tc[j] - tc[j - 1]) : 0.0;
             e.tp = (j < nt - 1) ? dr[i] * std::sin(tf[j + 1]) / (tc[j + 1] - tc[j]) : 0.0;
             e.s = e.rm + e.rp + e.tm + e.tp + dtop;
             e.pq = dr[i] * dt[j] / sj;
+            rows[(size_t)i * nt + j] = e;
         }
     }
+    for (int k = 0; k < np; ++k) {
+        dphi[k] = pf[k + 1] - pf[k];
+        const double gap = (k < np - 1) ? pc[k + 1] - pc[k] : pc[0] + kTwoPi - pc[np - 1];
+        ih[k] = 1.0 / gap;
+    }
+    for (int j = 0; j < nt; ++j) bfac[j] = std::sin(tc[j]) * dt[j] * rf[0] * rf[0];
+    double sr = 0.0, st = 0.0, sp = 0.0;
+    for (int i = 0; i < nr; ++i) sr += (vr[i] = rc[i] * rc[i] * dr[i]);
+    for (int j = 0; j < nt; ++j) st += (vt[j] = std::sin(tc[j]) * dt[j]);
+    for (int k = 0; k < np; ++k) sp += dphi[k];
+    *inv_volume = 1.0 / (sr * st * sp);
+}
+
+void build_tables(pot3d_ctx *c)
+{
+    const int nr = c->nr, nt = c->nt, np = c->np;
+    const double *rf = c->rf.data(), *tf = c->tf.data();
+    std::vector<double> work((size_t)2 * nr + 2 * nt + np);
+    c->rows_h.assign((size_t)nr * nt, RowCoef{});
     c->dphi_h.resize(np);
     c->ih_h.resize(np);
-    for (int k = 0; k < np; ++k) {
-        c->dphi_h[k] = pf[k + 1] - pf[k];
-        const double gap = (k < np - 1) ? pc[k + 1] - pc[k] : pc[0] + kTwoPi - pc[np - 1];
-        c->ih_h[k] = 1.0 / gap;
-    }
     c->bfac_h.resize(nt);
-    for (int j = 0; j < nt; ++j) c->bfac_h[j] = std::sin(tc[j]) * dt[j] * rf[0] * rf[0];
     c->vr_h.resize(nr);
     c->vt_h.resize(nt);
-    double sr = 0.0, st = 0.0, sp = 0.0;
-    for (int i = 0; i < nr; ++i) sr += (c->vr_h[i] = rc[i] * rc[i] * dr[i]);
-    for (int j = 0; j < nt; ++j) st += (c->vt_h[j] = std::sin(tc[j]) * dt[j]);
-    for (int k = 0; k < np; ++k) sp += c->dphi_h[k];
-    c->inv_volume = 1.0 / (sr * st * sp);
+    fill_tables(nr, nt, np, rf, tf, c->pf.data(), c->upper_bc, c->rows_h.data(), c->dphi_h.data(), c->ih_h.data(),
+                c->bfac_h.data(), c->vr_h.data(), c->vt_h.data(), &c->inv_volume, work.data());
+    const double *rc = work.data(), *tc = rc + 2 * nr;
     // field output: inverse centre spacings of the r- and theta-faces (0 where
     // the face carries the boundary value or no field), 1 / r_i, 1 / sin(theta_j)
     c->ftab_h.assign((size_t)(nr + 1) + (nt + 1) + nr + nt, 0.0);
@@ -150,7 +163,7 @@ void build_tables(pot3d_ctx *c)
 //   8/16/32 = workgroup tiles of that many polar rows x 64 cells (LDS plane);
 //   102/104/108 = wavefront tiles of 2/4/8 rows x 128 cells.
 // Radial chunks are sized so that one launch has about `target` workgroups.
-GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed = 0)
+GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed)
 {
     const int rows = tile_rows(tile), cols = tile_cols(tile);
     const int ntj = (c->nt + rows - 1) / rows;
@@ -337,7 +350,7 @@ void choose_launch(pot3d_ctx *c)
     const int hbm_ci = (hbm_shape && env_int("POT3D_CI", 0) <= 0 && tb <= 0) ? 16 : 0;
     c->grid_p = make_grid(c, c->tile_p, tp > 0 ? tp : dflt_target(kUpdateP, c->tile_p), tp > 0 ? 0 : hbm_ci);
     c->grid_r = make_grid(c, c->tile_r, tr > 0 ? tr : dflt_target(kUpdateR, c->tile_r), tr > 0 ? 0 : hbm_ci);
-    c->grid_o = make_grid(c, c->tile_o, tb > 0 ? tb : 2048);
+    c->grid_o = make_grid(c, c->tile_o, tb > 0 ? tb : 2048, 0);
     // The r/x update walks the tiles in the opposite order to the p update, so
     // each pass starts on the tiles the previous pass touched last, while their
     // lines may still sit in the 256 MB memory-side cache.
@@ -369,6 +382,9 @@ void fill_shape(const pot3d_ctx *c, pot3d_stats &st)
     st.sweep_rows = c->sweep_rows;
     st.chunk_s = c->grid_s.ci;
     st.blocks_s = c->grid_s.nblocks;
+    st.precond = c->precond;
+    st.blocks_l = c->precond == POT3D_PC_PHI_LINE ? c->line_blocks : 0;
+    if (c->precond == POT3D_PC_PHI_LINE) st.iteration = POT3D_ITER_TWO_PASS;
 }
 
 void set_tables(pot3d_ctx *c)
@@ -466,6 +482,47 @@ int capture_sweeps(pot3d_ctx *c, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *s
     return POT3D_OK;
 }
 
+// Capture m PCG iterations with the phi-line block preconditioner: the
+// direction update on z (p = z + beta p_old, A p, p.Ap), alpha, the r/x
+// update, the line pass (z = M^-1 r, r.z, r.r), then beta and convergence.
+int capture_line_iterations(pot3d_ctx *c, hipGraphExec_t *out)
+{
+    hipStream_t s = c->stream;
+    HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    double *pb[2] = {c->p[0], c->p[1]};
+    for (int it = 0; it < c->graph_m && e == hipSuccess; ++it) {
+        StencilVecs<double> a = base_vecs(c);
+        a.in = c->z;
+        a.pold = pb[it & 1];
+        a.pnew = pb[(it + 1) & 1];
+        a.zin = 1;
+        e = launch_stencil<double>(kUpdateP, c->tile_p, c->grid_p, a, s);
+        if (e == hipSuccess) e = launch_finish(kFinSigma, c->sc, c->partial, c->grid_p.nblocks, s);
+        if (e == hipSuccess) {
+            StencilVecs<double> bv = base_vecs(c);
+            bv.in = pb[(it + 1) & 1];
+            bv.r = c->r;
+            bv.x = c->x;
+            bv.zin = 1;
+            e = launch_stencil<double>(kUpdateR, c->tile_r, c->grid_r, bv, s);
+        }
+        if (e == hipSuccess) e = launch_line(c->grid_o, c->r, c->z, c->partial, c->line_blocks, c->sc, 0, s);
+        if (e == hipSuccess) e = launch_finish(kFinRho, c->sc, c->partial, c->line_blocks, s);
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(c, POT3D_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    }
+    if (e2 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(c, POT3D_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    return POT3D_OK;
+}
+
 // Replay `graph` (`per_graph` iterations each) until the scalar block `sc`
 // reports done, keeping one graph queued ahead of the poll.  Returns
 // POT3D_OK or a HIP error status.
@@ -503,13 +560,14 @@ void free_ctx(pot3d_ctx *c)
     if (c->graph) (void)hipGraphExecDestroy(c->graph);
     if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
     if (c->graph_s) (void)hipGraphExecDestroy(c->graph_s);
+    if (c->graph_l) (void)hipGraphExecDestroy(c->graph_l);
     if (c->graph32s) (void)hipGraphExecDestroy(c->graph32s);
     for (hipEvent_t *e : {&c->ev_poll[0], &c->ev_poll[1], &c->ev_t0, &c->ev_t1, &c->ev_loop0, &c->ev_loop1})
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
                     c->bplane, c->br, c->partial, c->poles, c->vr, c->vt, c->bcs, c->ftab, c->sc,
-                    c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32};
+                    c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32, c->z};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -579,10 +637,17 @@ int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit)
     rv.ignore_done = 1;
     HIP_TRY(c, launch_stencil<double>(kResidual, c->tile_o, c->grid_o, rv, s));
     HIP_TRY(c, launch_finish(kFinInit, c->sc, c->partial, c->grid_o.nblocks, s));
+    if (c->precond == POT3D_PC_PHI_LINE) {
+        // z = M^-1 r of the starting residual and rho = r.z (the first
+        // direction update then forms p = z)
+        HIP_TRY(c, launch_line(c->grid_o, c->r, c->z, c->partial, c->line_blocks, c->sc, 1, s));
+        HIP_TRY(c, launch_finish(kFinLineInit, c->sc, c->partial, c->line_blocks, s));
+    }
     return POT3D_OK;
 }
 
-// FP64 Jacobi-PCG: start, then graph replays (one-sweep or two-pass) until done.
+// FP64 PCG: start, then graph replays (one-sweep, two-pass, or with the
+// phi-line preconditioner) until done.
 int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t s, double tol, int maxit, int *iters,
              double *relres_true)
 {
@@ -591,12 +656,14 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     HIP_TRY(c, hipEventRecord(c->ev_loop0, s));
     int launches = 0;
     DevScalars fin{};
-    const bool sweep = one_sweep(c);
-    rc = replay_until_done(c, sweep ? c->graph_s : c->graph, c->sc, s, maxit, sweep ? 2 * c->graph_m : c->graph_m,
-                           &launches, &fin);
+    const bool line = c->precond == POT3D_PC_PHI_LINE;
+    const bool sweep = !line && one_sweep(c);
+    hipGraphExec_t graph = line ? c->graph_l : (sweep ? c->graph_s : c->graph);
+    rc = replay_until_done(c, graph, c->sc, s, maxit, sweep ? 2 * c->graph_m : c->graph_m, &launches, &fin);
     if (rc != POT3D_OK) return rc;
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, sweep ? 48.0 : 64.0, iters, relres_true);
+    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, line ? 80.0 : (sweep ? 48.0 : 64.0), iters,
+                        relres_true);
 }
 
 // Refinement, outer step: r = b - A x in FP64, then the outer test.  The
@@ -1209,6 +1276,32 @@ int pot3d_apply_device(pot3d_ctx *ctx, const double *d_x, double *d_y, void *str
     return POT3D_OK;
 }
 
+int pot3d_precondition_device(pot3d_ctx *ctx, const double *d_r, double *d_z, void *stream)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (!d_r || !d_z) return fail(ctx, POT3D_EINVAL, "r or z is NULL");
+    if (d_r == d_z) return fail(ctx, POT3D_EINVAL, "r and z must be distinct");
+    if (ctx->precision != POT3D_FP64) return fail(ctx, POT3D_EINVAL, "FP64 contexts only");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = stream ? reinterpret_cast<hipStream_t>(stream) : ctx->stream;
+    const size_t rowb = (size_t)ctx->np * sizeof(double), pitchb = (size_t)ctx->pitch * sizeof(double);
+    const size_t nrows = (size_t)ctx->nr * ctx->nt;
+    HIP_TRY(ctx, copy_rows(ctx->r, pitchb, d_r, rowb, rowb, nrows, hipMemcpyDeviceToDevice, s));
+    double *zpad = ctx->p[1];
+    if (ctx->precond == POT3D_PC_PHI_LINE) {
+        zpad = ctx->z;
+        HIP_TRY(ctx, launch_line(ctx->grid_o, ctx->r, zpad, ctx->partial, ctx->line_blocks, ctx->sc, 1, s));
+    } else {
+        HIP_TRY(ctx, launch_jacobi(ctx->grid_o, ctx->r, zpad, s));
+    }
+    HIP_TRY(ctx, copy_rows(d_z, rowb, zpad, pitchb, rowb, nrows, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (const unsigned line = take_oob_line(s))
+        return fail(ctx, POT3D_EDEVICE, "checked build: out-of-range index at kernels.hip line " + std::to_string(line));
+    return POT3D_OK;
+}
+
 int pot3d_rhs_device(pot3d_ctx *ctx, const double *d_br, double *d_b, void *stream)
 {
     if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
@@ -1266,7 +1359,9 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     out->pitch = ctx->pitch;
     fill_shape(ctx, *out);
     const bool fp32 = ctx->precision == POT3D_FP32_REFINED;
-    out->bytes_per_iter = (one_sweep(ctx) ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0)) * (double)ctx->n;
+    const double per = ctx->precond == POT3D_PC_PHI_LINE ? 80.0
+                       : one_sweep(ctx) ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0);
+    out->bytes_per_iter = per * (double)ctx->n;
     return POT3D_OK;
 }
 
@@ -1306,6 +1401,40 @@ int pot3d_set_iteration(pot3d_ctx *ctx, int iteration)
     if (iteration == POT3D_ITER_ONE_SWEEP && !ctx->graph_s && !ctx->graph32s)
         return fail(ctx, POT3D_EINVAL, "the one-sweep iteration needs vectors under 4 GiB");
     ctx->iteration = iteration;
+    return POT3D_OK;
+}
+
+int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc)
+{
+    if (!ctx) return fail(nullptr, POT3D_EINVAL, "ctx is NULL");
+    if (pc != POT3D_PC_JACOBI && pc != POT3D_PC_PHI_LINE)
+        return fail(ctx, POT3D_EINVAL, "pc must be POT3D_PC_JACOBI or POT3D_PC_PHI_LINE");
+    if (pc == POT3D_PC_JACOBI) {
+        ctx->precond = pc;
+        return POT3D_OK;
+    }
+    if (ctx->precision != POT3D_FP64 || ctx->serving)
+        return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner runs FP64 single solves only");
+    if (ctx->np > kMaxLineCells)
+        return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner takes at most 2048 azimuthal cells");
+    const double h = kTwoPi / ctx->np;
+    for (int k = 0; k < ctx->np; ++k)
+        if (std::fabs(ctx->dphi_h[k] - h) > 1e-12 * h)
+            return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner needs uniform phi faces");
+    DeviceGuard guard(ctx->device);
+    if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
+    if (!ctx->z) {
+        HIP_TRY(ctx, dalloc(&ctx->z, (size_t)ctx->npad));
+        HIP_TRY(ctx, launch_fill<double>(ctx->z, ctx->npad, 0.0, ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    if (!ctx->graph_l) {
+        const long long rows = (long long)ctx->nr * ctx->nt;
+        ctx->line_blocks = (int)std::max<long long>(1, std::min<long long>((rows + kWaves - 1) / kWaves, ctx->max_blocks));
+        const int rc = capture_line_iterations(ctx, &ctx->graph_l);
+        if (rc != POT3D_OK) return rc;
+    }
+    ctx->precond = pc;
     return POT3D_OK;
 }
 

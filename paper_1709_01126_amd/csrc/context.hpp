@@ -72,6 +72,13 @@ struct pot3d_ctx {
     hipGraphExec_t graph_s = nullptr;     // FP64 sweeps
     hipGraphExec_t graph32s = nullptr;    // FP32 inner sweeps
 
+    // Preconditioner of FP64 single solves: point Jacobi (PC1) or the phi-line
+    // blocks, which iterate in two passes plus a line pass that writes z.
+    int precond = POT3D_PC_JACOBI;
+    double *z = nullptr;          // phi-line: z = M^-1 r
+    int line_blocks = 0;          // workgroups of a line pass
+    hipGraphExec_t graph_l = nullptr;
+
     bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;
     bool field_ready = false;     // x and the b plane belong to the last solve
@@ -115,6 +122,17 @@ struct DeviceGuard {
 void default_tiles(int precision, int *tile_p, int *tile_r);
 int validate_grid(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,
                   int precision, pot3d_ctx **out);
+// The operator's separable tables from the faces (see api.hip): rows
+// (nr * nt), dphi, ih (np), bfac (nt), vr (nr), vt (nt), 1 / shell volume;
+// work holds 2 nr + 2 nt + np doubles.  Allocates nothing.
+void fill_tables(int nr, int nt, int np, const double *rf, const double *tf, const double *pf, int upper_bc,
+                 RowCoef *rows, double *dphi, double *ih, double *bfac, double *vr, double *vt, double *inv_volume,
+                 double *work);
+// Launch shapes from the grid fields of c (nr, nt, np, pitch, npad,
+// precision, num_cu): a stencil pass of `tile` with about `target`
+// workgroups, and the one-sweep kernel with `rows` box rows per wavefront.
+GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed);
+GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target);
 // Allocate a context on `device` (tables, vectors, graphs).  serving = true:
 // no graph capture (the server's batched graph iterates it).
 int create_context(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,

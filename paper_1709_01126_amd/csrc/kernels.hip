@@ -209,8 +209,9 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
     // loaded value.  Masked by multiplication (clamped data are finite).
     auto eval = [&](V a, V bold, const RowCoef &rc, V pdph, V pihm, V pihk, V mask) -> V {
         if constexpr (MODE == kUpdateP) {
-            const V d = diag_at<V>(rc, pdph + (V(1) - mask), pihm, pihk);
-            return vfma<V>(beta, bold, a / d) * mask;
+            // z = D^-1 r, or the operand itself when it is z already (block preconditioner)
+            const V z = v.zin ? a : a / diag_at<V>(rc, pdph + (V(1) - mask), pihm, pihk);
+            return vfma<V>(beta, bold, z) * mask;
         } else {
             return a * mask;
         }
@@ -326,9 +327,11 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
                     const V rn = vfma<V>(-alpha, ap, rv[m]);
                     stream_store(gout + idx, rn);
                     stream_store(gout2 + idx, vfma<V>(alpha, pc, xv[m]));
-                    const V z = rn / diag_at<V>(r_, dph, ihm, ihk);
-                    acc0 += (double)rn * (double)z;
-                    acc1 += (double)rn * (double)rn;
+                    if (!v.zin) {   // with a block preconditioner the line pass takes r.z and r.r
+                        const V z = rn / diag_at<V>(r_, dph, ihm, ihk);
+                        acc0 += (double)rn * (double)z;
+                        acc1 += (double)rn * (double)rn;
+                    }
                 }
             }
         }
@@ -549,8 +552,10 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
         auto eval_row = [&](const Raw &q, const RowCoef &rc, bool on, V &a0, V &a1) {
             V e0, e1;
             if constexpr (MODE == kUpdateP) {
-                e0 = vfma<V>(beta, q.b.x, q.a.x / diag_at<V>(rc, dph0 + (V)(!v0), ihm0, ihk0));
-                e1 = vfma<V>(beta, q.b.y, q.a.y / diag_at<V>(rc, dph1 + (V)(!v1), ihm1, ihk1));
+                const V z0 = v.zin ? q.a.x : q.a.x / diag_at<V>(rc, dph0 + (V)(!v0), ihm0, ihk0);
+                const V z1 = v.zin ? q.a.y : q.a.y / diag_at<V>(rc, dph1 + (V)(!v1), ihm1, ihk1);
+                e0 = vfma<V>(beta, q.b.x, z0);
+                e1 = vfma<V>(beta, q.b.y, z1);
             } else {
                 e0 = q.a.x;
                 e1 = q.a.y;
@@ -574,7 +579,8 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
             return q;
         };
         auto eval_cell = [&](const RawCell &q, const RowCoef &rc, V cdph, V cihm, V cihk) -> V {
-            if constexpr (MODE == kUpdateP) return vfma<V>(beta, q.b, q.a / diag_at<V>(rc, cdph, cihm, cihk));
+            if constexpr (MODE == kUpdateP)
+                return vfma<V>(beta, q.b, v.zin ? q.a : q.a / diag_at<V>(rc, cdph, cihm, cihk));
             else return q.a;
         };
         auto store2 = [&](GPtr<V> dst, int ip, int j, V a0, V a1) {
@@ -708,9 +714,11 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
                     for (int e = 0; e < 2; ++e) {
                         rn[e] = ve[e] ? vfma<V>(-alpha, ap[e], rr[e]) : V(0);
                         xn[e] = ve[e] ? vfma<V>(alpha, cc[e], xx[e]) : V(0);
-                        const V z = rn[e] / diag_at<V>(r_, dph[e] + (V)(!ve[e]), ihm[e], ihk[e]);
-                        acc0 += wrow * ((double)rn[e] * (double)z);
-                        acc1 += wrow * ((double)rn[e] * (double)rn[e]);
+                        if (!v.zin) {   // with a block preconditioner the line pass takes the sums
+                            const V z = rn[e] / diag_at<V>(r_, dph[e] + (V)(!ve[e]), ihm[e], ihk[e]);
+                            acc0 += wrow * ((double)rn[e] * (double)z);
+                            acc1 += wrow * ((double)rn[e] * (double)rn[e]);
+                        }
                     }
                     if (row_on) {
                         store2(gout, i, j, rn[0], rn[1]);
@@ -1167,7 +1175,7 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
     double s[kMaxPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int ncomp = (which == kFinSigma) ? 1
                       : (which == kFinSweep) ? 5
-                      : ((which == kFinInit || which == kFinOuter) ? 3 : 2);
+                      : ((which == kFinInit || which == kFinOuter) ? 3 : 2);   // kFinLineInit: 2
     block_sums(partial, nb, ncomp, s);
     if (threadIdx.x != 0) return;
     if (which == kFinInit) {
@@ -1279,6 +1287,10 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
             }
         }
         if (stop) sc->done = 1;
+    } else if (which == kFinLineInit) {
+        // Block preconditioner: the start's rho is r.z with z = M^-1 r from the
+        // line pass (kFinInit took ||b|| and the first residual test).
+        sc->rho = s[0];
     } else if (which == kFinTrue) {  // ||b - A x|| / ||b|| from a residual pass with store_r = 0
         sc->relres_true = (sc->bnorm > 0.0) ? sqrt(s[1]) / sc->bnorm : 0.0;
     } else if (which == kFinOuter) {
@@ -1348,6 +1360,256 @@ finish_batch(int which, const BatchFin *__restrict__ fins, int nslots)
     const int q = blockIdx.x;
     if (q >= nslots || !fins[q].active) return;
     finish_body(which, fins[q].sc, fins[q].partial, fins[q].nb);
+}
+
+// ---------------------------------------------------------------------------
+// phi-line block preconditioner: z = M^-1 r, where M keeps, for every (i, j)
+// row, the diagonal of A and its two periodic azimuthal weights, and drops
+// every coupling between rows (a stronger preconditioner than the point
+// Jacobi of Sec. 2.3: near the poles the azimuthal weights, which carry
+// 1 / sin(theta), dominate the diagonal).
+//
+// On a uniform phi grid the block of row (i, j) is the circulant
+//     d I - w (S + S^-1),   w = pq / dphi,   d = dphi s + 2 w
+// (S: the periodic shift by one cell), which factors as
+//     (w / mu) (I - mu S) (I - mu S^-1),   mu + 1/mu = d / w,  0 < mu < 1.
+// So z = (mu / w) v with two first-order periodic recurrences
+//     u_k = r_k + mu u_{k-1},     v_k = u_k + mu v_{k+1}        (k mod np).
+// With d / (2 w) = 1 + e, mu = 1 / (1 + e + sqrt(e (2 + e))), free of
+// cancellation for small e (pole rows) and large e alike.
+//
+// One wavefront solves one row, cell k = 64 q + lane in block q.  Each
+// recurrence runs over the blocks in order: an inclusive scan across the 64
+// lanes (lane shuffles with multipliers mu^1, mu^2, mu^4, ..), plus the carry
+// from the neighbouring block times the power of mu that it travels.  The
+// periodic wrap is closed afterwards: the value that comes round the row is
+// the non-periodic end value divided by 1 - mu^np, and it enters every cell
+// with its own power of mu.  Every value is FP64; each row reads r once and
+// writes z once (16 bytes per unknown), keeping a copy of r in LDS for r.z.
+// Per-workgroup partial sums of r.z and r.r follow in fixed order.
+// ---------------------------------------------------------------------------
+// m^e for an integer e >= 0 by binary powering.
+__device__ __forceinline__ double powi(double m, int e)
+{
+    double r = 1.0;
+    while (e > 0) {
+        if (e & 1) r *= m;
+        m *= m;
+        e >>= 1;
+    }
+    return r;
+}
+
+// A double moved across lanes by a DPP row shift (row_shr:n is 0x110 + n,
+// row_shl:n is 0x100 + n; rows are 16 lanes).  Lanes whose source lies
+// outside their row receive 0.
+template <int CTRL>
+__device__ __forceinline__ double row_shift(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// The value of v in lane l (uniform l), as a wave-uniform double.
+__device__ __forceinline__ double lane_value(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// One block of 64 cells of a first-order recurrence, carried in from the
+// previous block.  Forward (UP): s_l = x_l + mu s_{l-1}, with s_{-1} = carry.
+// Backward: s_l = x_l + mu s_{l+1}, with s_64 = carry.  First an inclusive
+// scan inside each 16-lane row (DPP shifts by 1, 2, 4, 8 with multipliers
+// mu, mu^2, mu^4, mu^8), then the rows are chained through their end values
+// (uniform), and each lane adds its row's entry value times mu^(distance).
+// Returns s_l; *carry becomes the value at the far end of the block.
+template <bool UP>
+__device__ __forceinline__ double block_recurrence(double x, double &carry, const double (&mpow)[5], double pw_row,
+                                                   int row)
+{
+    double sv = x;
+    if (UP) {
+        sv = __builtin_fma(mpow[0], row_shift<0x111>(sv), sv);
+        sv = __builtin_fma(mpow[1], row_shift<0x112>(sv), sv);
+        sv = __builtin_fma(mpow[2], row_shift<0x114>(sv), sv);
+        sv = __builtin_fma(mpow[3], row_shift<0x118>(sv), sv);
+        // row r ends at lane 16 r + 15; P_r is the value just before row r
+        const double e0 = lane_value(sv, 15), e1 = lane_value(sv, 31), e2 = lane_value(sv, 47),
+                     e3 = lane_value(sv, 63);
+        const double p0 = carry;
+        const double p1 = __builtin_fma(mpow[4], p0, e0);
+        const double p2 = __builtin_fma(mpow[4], p1, e1);
+        const double p3 = __builtin_fma(mpow[4], p2, e2);
+        carry = __builtin_fma(mpow[4], p3, e3);
+        const double pin = row == 0 ? p0 : row == 1 ? p1 : row == 2 ? p2 : p3;
+        return __builtin_fma(pw_row, pin, sv);   // pw_row = mu^(lane % 16 + 1)
+    } else {
+        sv = __builtin_fma(mpow[0], row_shift<0x101>(sv), sv);
+        sv = __builtin_fma(mpow[1], row_shift<0x102>(sv), sv);
+        sv = __builtin_fma(mpow[2], row_shift<0x104>(sv), sv);
+        sv = __builtin_fma(mpow[3], row_shift<0x108>(sv), sv);
+        // row r starts at lane 16 r; Q_r is the value just after row r
+        const double b0 = lane_value(sv, 0), b1 = lane_value(sv, 16), b2 = lane_value(sv, 32),
+                     b3 = lane_value(sv, 48);
+        const double q3 = carry;
+        const double q2 = __builtin_fma(mpow[4], q3, b3);
+        const double q1 = __builtin_fma(mpow[4], q2, b2);
+        const double q0 = __builtin_fma(mpow[4], q1, b1);
+        carry = __builtin_fma(mpow[4], q0, b0);
+        const double qin = row == 0 ? q0 : row == 1 ? q1 : row == 2 ? q2 : q3;
+        return __builtin_fma(pw_row, qin, sv);   // pw_row = mu^(16 - lane % 16)
+    }
+}
+
+// NB = blocks of 64 cells per row (np in (64 (NB - 1), 64 NB]).
+template <int NB>
+__global__ void __launch_bounds__(kThreads)
+line_solve_kernel(GridArgs g, const double *__restrict__ rin, double *__restrict__ zout, double *__restrict__ partial,
+                  const DevScalars *__restrict__ sc, int ignore_done)
+{
+    const CPtr<const DevScalars> csc = to_const(sc);
+    if (!ignore_done && csc->done) return;   // uniform over the workgroup
+    __shared__ double red[kWaves][2];
+    const GPtr<const double> gr = to_global(rin);
+    const GPtr<double> gz = to_global(zout);
+    const CPtr<const RowCoef> crows = to_const(g.rows);
+    const int np = g.np;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int row16 = lane >> 4, rl = lane & 15;
+    const int nl = np - kWave * (NB - 1);        // cells in the last block (1..64)
+    const bool lane_last = lane < nl;            // this lane holds a cell of the last block
+    const double dph = to_global(g.dphi)[0];     // uniform phi: every width is 2 pi / np
+    const double ih = to_global(g.ih)[0];
+    const long long nrows = (long long)g.nr * g.nt;
+    double acc_rz = 0.0, acc_rr = 0.0;
+
+    for (long long row = (long long)blockIdx.x * kWaves + w; row < nrows; row += (long long)gridDim.x * kWaves) {
+        const RowCoef rc = load_row(crows, CHK(row, nrows));
+        const long long base = row * g.pitch;
+        double rv[NB], u[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int k = q * kWave + lane;
+            rv[q] = (q < NB - 1 || lane_last) ? stream_load(gr + CHK(base + k, g.npad)) : 0.0;
+        }
+        const double wgt = rc.pq * ih;                       // azimuthal weight w
+        const double e = dph * rc.s / (2.0 * wgt);           // d / (2 w) - 1 > 0
+        const double mu = 1.0 / (1.0 + e + sqrt(e * (2.0 + e)));
+        double mpow[5];                                       // mu, mu^2, mu^4, mu^8, mu^16
+        mpow[0] = mu;
+#pragma unroll
+        for (int t = 1; t < 5; ++t) mpow[t] = mpow[t - 1] * mpow[t - 1];
+        const double mu64 = (mpow[4] * mpow[4]) * (mpow[4] * mpow[4]);
+        const double inv_wrap = 1.0 / (1.0 - powi(mu, np));  // 1 / (1 - mu^np)
+        const double pw_fw = powi(mu, rl + 1);                // mu^(lane % 16 + 1)
+        const double pw_bw = powi(mu, 16 - rl);               // mu^(16 - lane % 16)
+
+        // forward: u_k = r_k + mu u_{k-1}, first without the wrap (u_{-1} = 0)
+        double carry = 0.0, ulast = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            u[q] = block_recurrence<true>(rv[q], carry, mpow, pw_fw, row16);
+            if (q == NB - 1) ulast = lane_value(u[q], nl - 1);   // u at cell np - 1
+        }
+        // the wrap: u_{np-1} = ulast / (1 - mu^np) enters cell k as mu^(k+1) u_{np-1}
+        {
+            double f = powi(mu, lane + 1) * (ulast * inv_wrap);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                u[q] = (q < NB - 1 || lane_last) ? u[q] + f : 0.0;
+                f *= mu64;
+            }
+        }
+        // backward: v_k = u_k + mu v_{k+1}, first without the wrap (v_np = 0)
+        carry = 0.0;
+#pragma unroll
+        for (int q = NB - 1; q >= 0; --q) u[q] = block_recurrence<false>(u[q], carry, mpow, pw_bw, row16);
+        // the wrap: v_0 = carry / (1 - mu^np) enters cell k as mu^(np-k) v_0;
+        // np - k is nl - lane in the last block and 64 more per block before it
+        const double v0 = carry * inv_wrap;
+        const double scale = mu / wgt;
+        double fb = powi(mu, nl - lane + kWave);
+#pragma unroll
+        for (int q = NB - 1; q >= 0; --q) {
+            const int k = q * kWave + lane;
+            double fe;
+            if (q == NB - 1) {
+                fe = lane_last ? powi(mu, nl - lane) : 0.0;
+            } else {
+                fe = fb;
+                fb *= mu64;
+            }
+            if (q < NB - 1 || lane_last) {
+                const double z = scale * __builtin_fma(fe, v0, u[q]);
+                stream_store(gz + CHK(base + k, g.npad), z);
+                acc_rz = __builtin_fma(rv[q], z, acc_rz);
+                acc_rr = __builtin_fma(rv[q], rv[q], acc_rr);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        acc_rz += __shfl_xor(acc_rz, off, kWave);
+        acc_rr += __shfl_xor(acc_rr, off, kWave);
+    }
+    if (lane == 0) {
+        red[w][0] = acc_rz;
+        red[w][1] = acc_rr;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) t += red[q][threadIdx.x];
+        to_global(partial)[CHK((long long)threadIdx.x * gridDim.x + blockIdx.x, 2LL * gridDim.x)] = t;
+    }
+}
+
+// Point Jacobi, z = D^-1 r over the padded layout (padding stays zero).
+__global__ void __launch_bounds__(256)
+jacobi_kernel(GridArgs g, const double *__restrict__ r, double *__restrict__ z)
+{
+    const long long nrows = (long long)g.nr * g.nt;
+    const CPtr<const RowCoef> crows = to_const(g.rows);
+    const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih);
+    for (long long row = blockIdx.x; row < nrows; row += gridDim.x) {
+        const RowCoef rc = load_row(crows, CHK(row, nrows));
+        for (int k = threadIdx.x; k < g.np; k += blockDim.x) {
+            const double d = diag_at<double>(rc, gdphi[CHK(k, g.np)], gih[CHK(k == 0 ? g.np - 1 : k - 1, g.np)],
+                                             gih[CHK(k, g.np)]);
+            const long long o = CHK(row * g.pitch + k, g.npad);
+            z[o] = r[o] / d;
+        }
+    }
+}
+
+hipError_t launch_jacobi(const GridArgs &g, const double *r, double *z, hipStream_t s)
+{
+    const long long nrows = (long long)g.nr * g.nt;
+    jacobi_kernel<<<(unsigned)std::min<long long>(nrows, 65536), 256, 0, s>>>(g, r, z);
+    return hipGetLastError();
+}
+
+template <int NB>
+static hipError_t launch_line_nb(int nb, const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
+                                 const DevScalars *sc, int ignore_done, hipStream_t s)
+{
+    if constexpr (NB > 1) {
+        if (nb < NB) return launch_line_nb<NB - 1>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
+    }
+    line_solve_kernel<NB><<<nblocks, kThreads, 0, s>>>(g, r, z, partial, sc, ignore_done);
+    return hipGetLastError();
+}
+
+hipError_t launch_line(const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
+                       const DevScalars *sc, int ignore_done, hipStream_t s)
+{
+    const int nb = (g.np + kWave - 1) / kWave;
+    if (nb < 1 || nb > kMaxLineCells / kWave) return hipErrorInvalidValue;
+    return launch_line_nb<kMaxLineCells / kWave>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,8 @@ enum FinWhich : int {
     kFinOuter = 4,  // refinement, after the FP64 residual pass: outer test, scale = 1/||r||
     kFinInner = 5,  // refinement, after the r.z pass on the FP32 residual: inner start
     kFinResume = 6, // refinement, reliable update: as kFinInner, keeping the direction
-    kFinSweep = 7   // one-sweep iteration: convergence test, alpha, predicted r.z, beta
+    kFinSweep = 7,  // one-sweep iteration: convergence test, alpha, predicted r.z, beta
+    kFinLineInit = 8  // block preconditioner, after the first line pass: rho = r.z
 };
 
 // Partial sums per workgroup that a finisher may read (the one-sweep kernel
@@ -82,6 +83,15 @@ hipError_t launch_field(const double *x, const double *bplane, const double *bfa
 // of the weights); partial holds nblocks doubles, *mean receives the mean.
 hipError_t launch_gauge(double *x, const double *vr, const double *vt, const double *dphi, int nr, int nt, int np,
                         int pitch, double inv_volume, double *partial, int nblocks, double *mean, hipStream_t s);
+
+// phi-line block preconditioner (uniform phi, np <= kMaxLineCells): z = M^-1 r
+// row by row, partial sums [0][b] = r.z and [1][b] = r.r for b < nblocks.
+constexpr int kMaxLineCells = 32 * 64;
+hipError_t launch_line(const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
+                       const DevScalars *sc, int ignore_done, hipStream_t s);
+
+// Point Jacobi z = D^-1 r (padded layout).
+hipError_t launch_jacobi(const GridArgs &g, const double *r, double *z, hipStream_t s);
 
 template <typename V>
 hipError_t launch_fill(V *p, long long n, V val, hipStream_t s);

@@ -86,6 +86,8 @@ struct StencilVecs {
     int ignore_done;  // 1: run even when sc->done is set
     unsigned long long *tstamp;   // timing runs only: [0] earliest workgroup start, [1] latest
                                   // workgroup end (device wall clock); NULL otherwise
+    int zin;          // block preconditioner: update-p reads z = M^-1 r (already
+                      // preconditioned) instead of r; update-r leaves r.z, r.r to the line pass
 };
 
 // Vectors of one sweep of the one-sweep iteration (sweep j: r_j from r_{j-1}

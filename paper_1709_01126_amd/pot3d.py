@@ -21,12 +21,13 @@ UPPER_SOURCE_SURFACE, UPPER_CLOSED_WALL = 0, 1
 FP64, FP32_REFINED = 0, 1
 REFINE_RESTART, REFINE_RELIABLE = 0, 1
 ITER_TWO_PASS, ITER_ONE_SWEEP = 0, 1
+PC_JACOBI, PC_PHI_LINE = 0, 1
 STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
                 EBREAKDOWN: "EBREAKDOWN"}
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
-            "pot3d_pole_values", "pot3d_field_device", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
-            "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_destroy",
+            "pot3d_precondition_device", "pot3d_pole_values", "pot3d_field_device", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
+            "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_set_preconditioner", "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
             "pot3d_server_set_cache_budget", "pot3d_server_get_stats", "pot3d_server_destroy",
@@ -40,7 +41,8 @@ class pot3d_stats(ctypes.Structure):
                 ("n", ctypes.c_longlong), ("pitch", ctypes.c_int), ("tile_p", ctypes.c_int),
                 ("tile_r", ctypes.c_int), ("chunk_p", ctypes.c_int), ("chunk_r", ctypes.c_int),
                 ("blocks_p", ctypes.c_int), ("blocks_r", ctypes.c_int), ("iteration", ctypes.c_int),
-                ("sweep_rows", ctypes.c_int), ("chunk_s", ctypes.c_int), ("blocks_s", ctypes.c_int)]
+                ("sweep_rows", ctypes.c_int), ("chunk_s", ctypes.c_int), ("blocks_s", ctypes.c_int),
+                ("precond", ctypes.c_int), ("blocks_l", ctypes.c_int)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -95,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_solve_device.restype = i
     lib.pot3d_apply_device.argtypes = [vp, vp, vp, vp]
     lib.pot3d_apply_device.restype = i
+    lib.pot3d_precondition_device.argtypes = [vp, vp, vp, vp]
+    lib.pot3d_precondition_device.restype = i
     lib.pot3d_rhs_device.argtypes = [vp, vp, vp, vp]
     lib.pot3d_rhs_device.restype = i
     lib.pot3d_pole_values.argtypes = [vp, d, d]
@@ -109,6 +113,8 @@ def load(path: str = LIB_PATH):
     lib.pot3d_set_refinement_mode.restype = i
     lib.pot3d_set_iteration.argtypes = [vp, i]
     lib.pot3d_set_iteration.restype = i
+    lib.pot3d_set_preconditioner.argtypes = [vp, i]
+    lib.pot3d_set_preconditioner.restype = i
     lib.pot3d_field_device.argtypes = [vp, vp, vp, vp, vp]
     lib.pot3d_field_device.restype = i
     lib.pot3d_destroy.argtypes = [vp]
@@ -253,6 +259,10 @@ def pot3d_apply_device(ctx, d_x, d_y, stream=None):
     return load().pot3d_apply_device(ctx, d_x, d_y, stream)
 
 
+def pot3d_precondition_device(ctx, d_r, d_z, stream=None):
+    return load().pot3d_precondition_device(ctx, d_r, d_z, stream)
+
+
 def pot3d_rhs_device(ctx, d_br, d_b, stream=None):
     return load().pot3d_rhs_device(ctx, d_br, d_b, stream)
 
@@ -289,6 +299,10 @@ def pot3d_set_refinement_mode(ctx, mode):
 
 def pot3d_set_iteration(ctx, iteration):
     return load().pot3d_set_iteration(ctx, int(iteration))
+
+
+def pot3d_set_preconditioner(ctx, pc):
+    return load().pot3d_set_preconditioner(ctx, int(pc))
 
 
 def pot3d_field_device(ctx, d_br, d_bt, d_bp, stream=None):
@@ -359,6 +373,19 @@ class Solver:
             stream = torch.cuda.current_stream(x.device)
         self._check(pot3d_apply_device(self.ctx, x.data_ptr(), y.data_ptr(), stream.cuda_stream), (OK,))
 
+    def precondition(self, r, z, stream=None):
+        """z = M^-1 r with the context's preconditioner (torch CUDA float64 tensors)."""
+        import torch
+
+        n = self.nr * self.nt * self.np
+        _dev_tensor(r, n, self.device, "r")
+        _dev_tensor(z, n, self.device, "z")
+        if r.data_ptr() == z.data_ptr():
+            raise ValueError("r and z must be distinct buffers")
+        if stream is None:
+            stream = torch.cuda.current_stream(r.device)
+        self._check(pot3d_precondition_device(self.ctx, r.data_ptr(), z.data_ptr(), stream.cuda_stream), (OK,))
+
     def rhs(self, br, b, stream=None):
         import torch
 
@@ -391,6 +418,9 @@ class Solver:
 
     def set_iteration(self, iteration):
         self._check(pot3d_set_iteration(self.ctx, iteration), (OK,))
+
+    def set_preconditioner(self, pc):
+        self._check(pot3d_set_preconditioner(self.ctx, pc), (OK,))
 
     def field(self, stream=None):
         """B = -grad Phi of the last solution on the cell faces, as torch CUDA

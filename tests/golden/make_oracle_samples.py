@@ -1,4 +1,5 @@
-"""Write sampled oracle results for a full-size workload to a small JSON fixture.
+"""Write sampled oracle results for a full-size workload to a small JSON fixture
+(point-Jacobi PCG, or with --precond phi_line the phi-line block preconditioner).
 
 Calls only ``oracle`` and ``workloads``.  The GPU parity tests at full size
 compare the solver's Phi at these seeded indices, its iteration count and its
@@ -55,17 +56,18 @@ def layer_functionals(x, seed=7):
     return {"seed": seed, "l2": l2, "sum": s1, "dot_randn": sv}
 
 
-def main(name, solve=True, save_phi=None):
+def main(name, solve=True, save_phi=None, precond="jacobi"):
     w = WORKLOADS[name]
     rf, tf, pf = w.faces()
     br = w.br((rf, tf, pf))
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
     idx = sample_indices(w.nr, w.nt, w.np)
+    suffix = "" if precond == "jacobi" else f"_{precond}"
     t0 = time.time()
     fixed = {}
     for K in FIXED_KS:
-        xk, itk, rrk, stk = oracle.pcg(coef, b, 0.0, K)
+        xk, itk, rrk, stk = oracle.pcg(coef, b, 0.0, K, precond=precond)
         fixed[str(K)] = {"relres": rrk, "phi": xk.ravel()[idx].tolist(), "phi_max_abs": float(np.abs(xk).max())}
     t1 = time.time()
     if not solve:
@@ -74,12 +76,12 @@ def main(name, solve=True, save_phi=None):
                           "written by tests/golden/make_oracle_samples.py (calls only oracle/ and workloads/)",
                "workload": name, "nr": w.nr, "nt": w.nt, "np": w.np, "tol": w.tol,
                "indices": idx.tolist(), "fixed": fixed, "oracle_seconds": {"fixed_k": t1 - t0}}
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}{suffix}.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=None, separators=(",", ":"))
         print(path, t1 - t0)
         return
-    x, iters, relres, st = oracle.pcg(coef, b, w.tol, 200_000)
+    x, iters, relres, st = oracle.pcg(coef, b, w.tol, 200_000, precond=precond)
     t2 = time.time()
     if save_phi:
         np.save(save_phi, x)
@@ -87,7 +89,7 @@ def main(name, solve=True, save_phi=None):
     out = {
         "_source": "oracle/pot3d_oracle.c Jacobi-PCG on the named seeded workload; written by "
                    "tests/golden/make_oracle_samples.py (calls only oracle/ and workloads/)",
-        "workload": name, "nr": w.nr, "nt": w.nt, "np": w.np, "tol": w.tol,
+        "workload": name, "nr": w.nr, "nt": w.nt, "np": w.np, "tol": w.tol, "precond": precond,
         "status": st, "iters": iters, "relres": relres,
         "true_relres": oracle.true_relres(coef, b, x),
         "phi_max_abs": float(np.abs(x).max()), "phi_l2": float(np.sqrt(oracle.dot(x, x))),
@@ -97,7 +99,7 @@ def main(name, solve=True, save_phi=None):
         "layers": layer_functionals(x),
         "oracle_seconds": {"fixed_k": t1 - t0, "solve": t2 - t1},
     }
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}.json")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"oracle_{name}{suffix}.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=None, separators=(",", ":"))
     print(path, iters, relres, out["true_relres"], t2 - t1)
@@ -105,6 +107,8 @@ def main(name, solve=True, save_phi=None):
 
 if __name__ == "__main__":
     # python tests/golden/make_oracle_samples.py NAME [--fixed-only] [--save-phi PATH.npy]
+    #                                             [--precond phi_line]
     sp = sys.argv[sys.argv.index("--save-phi") + 1] if "--save-phi" in sys.argv else None
+    pc = sys.argv[sys.argv.index("--precond") + 1] if "--precond" in sys.argv else "jacobi"
     main(sys.argv[1] if len(sys.argv) > 1 else "bipole_151x301x601", solve="--fixed-only" not in sys.argv,
-         save_phi=sp)
+         save_phi=sp, precond=pc)

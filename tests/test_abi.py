@@ -113,6 +113,8 @@ def test_null_arguments():
     assert lib.pot3d_solve(None, P._dp(br), 1e-10, 10, None, P._dp(phi), None, None) == P.EINVAL
     assert P.pot3d_solve_device(None, 1, None, 1, None, 1e-10, 10)[0] == P.EINVAL
     assert P.pot3d_apply_device(None, 1, 2) == P.EINVAL
+    assert P.pot3d_precondition_device(None, 1, 2) == P.EINVAL
+    assert P.pot3d_set_preconditioner(None, P.PC_PHI_LINE) == P.EINVAL
     assert P.pot3d_rhs_device(None, 1, 2) == P.EINVAL
     north, south = np.empty(4), np.empty(4)
     assert lib.pot3d_pole_values(None, P._dp(north), P._dp(south)) == P.EINVAL

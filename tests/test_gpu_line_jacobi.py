@@ -1,0 +1,180 @@
+"""GPU parity of the phi-line block preconditioner against the FP64 oracle.
+
+M keeps the diagonal of A and its two periodic azimuthal weights on every
+(r, theta) row and drops the couplings between rows (a stronger
+preconditioner than the point Jacobi "PC1" of Sec. 2.3, of the kind Sec. 6
+asks for).  The oracle solves each row by Thomas elimination with a
+Sherman-Morrison correction for the corners; the library factors the
+circulant row of a uniform phi grid into two first-order periodic
+recurrences.  Bars:
+* z = M^-1 r: per row, max |z_gpu - z_orc| <= 1e-10 max |z_orc|.  The row's
+  smallest eigenvalue is its non-azimuthal part, a fraction e of the diagonal
+  (e >= ~1e-5 on these grids); the oracle's diagonal is a rounded sum of
+  seven weights and the library's a product of table values, so the two
+  blocks differ by a few ulps of the diagonal, which moves z by up to about
+  4 eps / e relative (< 1e-10 here).
+* point Jacobi through the same entry point: z = r / diag(A) to 1e-15.
+* solves at tol 1e-10: ||Phi_gpu - Phi_orc|| <= 1e-8 ||Phi_orc|| (2-norm and
+  max), iterations within max(2, 0.5 %), both sides line-preconditioned.
+* fixed count (tol = 0, K iterations): iterates agree to 1e-11, the point
+  Jacobi bar (measured 1.5e-14 at K = 20 on 20 x 37 x 101: the block
+  difference above is largest on the few pole rows and CG damps it there).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1709_01126_amd import pot3d as P
+from workloads import grids, magnetograms
+
+from test_gpu_parity import dev, gpu_solve, iters_close, make_faces
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LINE_GRIDS = [
+    (2, 2, 3, "stretched", "uniform", "uniform"),
+    (3, 4, 6, "uniform", "uniform", "uniform"),
+    (6, 10, 40, "stretched", "ratio3", "uniform"),      # one partial block
+    (5, 8, 64, "stretched", "ratio3", "uniform"),       # exactly one block
+    (5, 8, 65, "stretched", "ratio3", "uniform"),       # one cell past a block
+    (20, 37, 101, "stretched", "ratio3", "uniform"),
+    (9, 33, 129, "stretched", "uniform", "uniform"),
+    (32, 64, 128, "stretched", "uniform", "uniform"),
+    (4, 9, 601, "stretched", "ratio3", "uniform"),      # the 151x301x601 row length
+    (3, 7, 1281, "stretched", "ratio3", "uniform"),     # the 301x641x1281 row length
+]
+
+
+def label(case):
+    return "x".join(str(v) for v in case[:3])
+
+
+def line_solver(rf, tf, pf, upper=P.UPPER_SOURCE_SURFACE):
+    s = P.Solver(rf, tf, pf, upper_bc=upper)
+    s.set_preconditioner(P.PC_PHI_LINE)
+    return s
+
+
+@pytest.fixture(scope="module", autouse=True)
+def announce():
+    print("\n[line] phi-line block preconditioner parity", flush=True)
+    yield
+
+
+@pytest.mark.parametrize("case", LINE_GRIDS, ids=label)
+def test_precondition_matches_oracle(case):
+    rf, tf, pf = make_faces(*case)
+    coef = oracle.assemble(rf, tf, pf)
+    r = np.random.default_rng(3).standard_normal(coef.shape[1:])
+    zo = oracle.line_solve(coef, r)
+    with line_solver(rf, tf, pf) as s:
+        z = torch.empty(r.shape, dtype=torch.float64, device="cuda:0")
+        s.precondition(dev(r), z)
+        torch.cuda.synchronize()
+        zg = z.cpu().numpy()
+    rowmax = np.abs(zo).max(axis=2, keepdims=True)
+    err = float((np.abs(zg - zo) / rowmax).max())
+    print(f"[line] {label(case)} M^-1 r: max row-relative diff {err:.2e}", flush=True)
+    assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("case", LINE_GRIDS[:6], ids=label)
+def test_jacobi_precondition_is_the_diagonal(case):
+    rf, tf, pf = make_faces(*case)
+    coef = oracle.assemble(rf, tf, pf)
+    r = np.random.default_rng(4).standard_normal(coef.shape[1:])
+    with P.Solver(rf, tf, pf) as s:
+        z = torch.empty(r.shape, dtype=torch.float64, device="cuda:0")
+        s.precondition(dev(r), z)
+        torch.cuda.synchronize()
+        zg = z.cpu().numpy()
+    want = r / coef[oracle.DIAG]
+    assert np.abs(zg - want).max() <= 1e-14 * np.abs(want).max()
+
+
+SOLVE_GRIDS = [LINE_GRIDS[i] for i in (2, 4, 5, 6, 7)]
+
+
+@pytest.mark.parametrize("case", SOLVE_GRIDS, ids=label)
+def test_line_pcg_solve_matches_oracle(case):
+    rf, tf, pf = make_faces(*case)
+    br, _ = magnetograms.br_harmonics(tf, pf, 4, seed=2)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000, precond="phi_line")
+    jac = oracle.solve(rf, tf, pf, br, tol, 100_000)
+    with line_solver(rf, tf, pf) as s:
+        phi, st, it, rr = gpu_solve(s, br, tol, 100_000)
+        stats = s.stats()
+    print(f"[line] {label(case)}: gpu {it} iterations, oracle {ref['iters']} (point Jacobi {jac['iters']}), "
+          f"true relres {rr:.2e}", flush=True)
+    assert st == P.OK and ref["status"] == oracle.OK
+    assert stats["precond"] == P.PC_PHI_LINE and stats["bytes_per_iter"] == 80.0 * phi.size
+    assert iters_close(it, ref["iters"]), (it, ref["iters"])
+    x = ref["phi"]
+    assert np.linalg.norm(phi - x) <= 1e-8 * np.linalg.norm(x)
+    assert np.abs(phi - x).max() <= 1e-8 * np.abs(x).max()
+    tr = oracle.true_relres(ref["coef"], ref["b"], phi)
+    assert abs(tr - rr) <= 1e-2 * tr + 1e-13 and tr <= tol * 1.5
+
+
+@pytest.mark.parametrize("K", [1, 5, 20])
+def test_line_pcg_fixed_count_iterates(K):
+    case = LINE_GRIDS[5]
+    rf, tf, pf = make_faces(*case)
+    br, _ = magnetograms.br_harmonics(tf, pf, 4, seed=5)
+    coef = oracle.assemble(rf, tf, pf)
+    b = oracle.rhs(rf, tf, pf, br)
+    xo, ito, _, sto = oracle.pcg(coef, b, 0.0, K, precond="phi_line")
+    with line_solver(rf, tf, pf) as s:
+        phi, st, it, _ = gpu_solve(s, br, 0.0, K)
+    assert st == P.ENOCONV and it == K and ito == K
+    err = np.abs(phi - xo).max() / np.abs(xo).max()
+    print(f"[line] fixed K={K}: max rel diff {err:.2e}", flush=True)
+    assert err <= 1e-11, err
+
+
+def test_line_pcg_closed_wall():
+    case = LINE_GRIDS[5]
+    rf, tf, pf = make_faces(*case)
+    br, _ = magnetograms.br_harmonics(tf, pf, 3, seed=6)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000, closed_wall=True, precond="phi_line")
+    with line_solver(rf, tf, pf, P.UPPER_CLOSED_WALL) as s:
+        phi, st, it, rr = gpu_solve(s, br, tol, 100_000)
+    assert st == P.OK and ref["status"] == oracle.OK
+    assert iters_close(it, ref["iters"]), (it, ref["iters"])
+    x = ref["phi"]
+    assert np.linalg.norm(phi - x) <= 1e-8 * np.linalg.norm(x)
+
+
+def test_line_pcg_switch_back_to_jacobi():
+    """The same context solves with either preconditioner, and point Jacobi
+    after the switch is unchanged."""
+    case = LINE_GRIDS[5]
+    rf, tf, pf = make_faces(*case)
+    br, _ = magnetograms.br_harmonics(tf, pf, 4, seed=2)
+    with P.Solver(rf, tf, pf) as s:
+        phi0, st0, it0, _ = gpu_solve(s, br, 1e-10, 100_000)
+        s.set_preconditioner(P.PC_PHI_LINE)
+        phil, stl, itl, _ = gpu_solve(s, br, 1e-10, 100_000)
+        s.set_preconditioner(P.PC_JACOBI)
+        phi1, st1, it1, _ = gpu_solve(s, br, 1e-10, 100_000)
+    assert st0 == stl == st1 == P.OK
+    assert it1 == it0 and np.array_equal(phi0, phi1)
+    assert itl < it0
+    assert np.linalg.norm(phil - phi0) <= 1e-7 * np.linalg.norm(phi0)
+
+
+def test_line_preconditioner_rejects_what_it_cannot_run():
+    rf, tf, pf = make_faces(4, 6, 8, "stretched", "ratio3", "jittered")
+    with P.Solver(rf, tf, pf) as s:
+        with pytest.raises(P.Pot3dError, match="uniform"):
+            s.set_preconditioner(P.PC_PHI_LINE)
+        with pytest.raises(P.Pot3dError):
+            s.set_preconditioner(7)
+    rf, tf, pf = make_faces(4, 6, 8, "stretched", "ratio3", "uniform")
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        with pytest.raises(P.Pot3dError, match="FP64"):
+            s.set_preconditioner(P.PC_PHI_LINE)
