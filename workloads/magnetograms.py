@@ -105,7 +105,8 @@ def br_bipoles(t_faces, p_faces, nbip: int, seed: int, dipole: float = 5.0) -> n
     +-2 sigma from its centre along the tilt bearing; a spot contributes
     +-F/(2 pi sigma^2) exp(-d^2 / (2 sigma^2)) at angular distance d.  Terms are
     evaluated only where d < 12 sigma (exp(-72) ~ 5e-32, below FP64 resolution
-    of the sum) so large maps stay cheap.
+    of the sum), and only on the rows and columns that can lie that close, so
+    large maps stay cheap.
     """
     tc, pc = sample_points(t_faces, p_faces)
     nt, nph = tc.size, pc.size
@@ -130,11 +131,24 @@ def br_bipoles(t_faces, p_faces, nbip: int, seed: int, dipole: float = 5.0) -> n
             jhi = np.searchsorted(tc, scol + reach, side="right")
             if jhi <= jlo:
                 continue
-            sub = pts[jlo:jhi]
+            # columns that can be within reach: a point within angular
+            # distance R of a centre at colatitude c differs from it in
+            # longitude by at most asin(sin R / sin c) when the cap misses the
+            # poles (otherwise every column); 0.01 rad of margin covers rounding
+            slon = math.atan2(s[1], s[0])
+            if scol - reach > 0.0 and scol + reach < math.pi:
+                half = math.asin(min(1.0, math.sin(reach) / math.sin(scol))) + 0.01
+                dl = np.abs(np.remainder(pc - slon + math.pi, 2.0 * math.pi) - math.pi)
+                cols = np.nonzero(dl <= half)[0]
+            else:
+                cols = np.arange(nph)
+            if cols.size == 0:
+                continue
+            sub = pts[jlo:jhi][:, cols]
             chord = np.linalg.norm(sub - s, axis=-1)
             d = 2.0 * np.arcsin(np.minimum(1.0, 0.5 * chord))
             m = d < reach
             contrib = np.zeros_like(d)
             contrib[m] = sgn * amp * np.exp(-0.5 * (d[m] / sigma) ** 2)
-            br[jlo:jhi] += contrib
+            br[jlo:jhi, cols] += contrib
     return br
