@@ -59,9 +59,10 @@ def load_traffic(workload: str, kernel: str):
 
 
 # algorithmic bytes per unknown of each iteration kernel, and the kernel-name
-# fragment that identifies it in a trace
-KERNEL_KEYS = {"sweep": (48.0, "stencil_sweep<"), "update_p": (24.0, ", 2, double>"),
-               "update_r": (40.0, ", 3, double>")}
+# fragments that identify it in a trace
+KERNEL_KEYS = {"sweep": (48.0, ("stencil_sweep<", "double")), "update_p": (24.0, (", 2, double>",)),
+               "update_r": (40.0, (", 3, double>",)), "sweep_fp32": (24.0, ("stencil_sweep<", "float")),
+               "line": (16.0, ("line_solve_kernel<",))}
 
 
 def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
@@ -91,8 +92,8 @@ def summarize_pmc(workload: str, fetch_dir: str, write_dir: str):
     f_scale = 8.0 * n / copy_fetch
     w_scale = 8.0 * n / copy_write
     kernels = {}
-    for key, (per_unknown, frag) in KERNEL_KEYS.items():
-        names = [k for k in fetch if "stencil_" in k and frag in k and "double" in k]
+    for key, (per_unknown, frags) in KERNEL_KEYS.items():
+        names = [k for k in fetch if all(f in k for f in frags)]
         if not names:
             continue
         name = names[0]
@@ -125,31 +126,122 @@ def kernel_name(stats, which):
     return f"stencil_march<{tile},{mode},double>"
 
 
+def host_cpu():
+    """The host's CPU model and core counts (from /proc/cpuinfo and the affinity mask)."""
+    model, logical, cores, cur = None, 0, set(), None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if ":" not in line:
+                continue
+            key, val = (t.strip() for t in line.split(":", 1))
+            if key == "processor":
+                logical += 1
+            elif key == "model name" and model is None:
+                model = val
+            elif key == "physical id":
+                cur = val
+            elif key == "core id":
+                cores.add((cur, val))
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": logical or os.cpu_count(), "physical_cores": len(cores) or None,
+            "usable_cpus": usable}
+
+
 def cpu_baseline(w, faces, br, budget_s: float):
+    """The oracle's fixed-count iterations on the host cores: all threads
+    OpenMP gives it (the value), then one thread (the paper's serial baseline,
+    Sec. 4.1) on a shorter sample."""
     import oracle
 
     rf, tf, pf = faces
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
-    # a warm-up run, two short runs to size the sample (per-iteration time and
-    # the per-call setup), then a run of about budget_s seconds
-    oracle.pcg(coef, b, 0.0, 1)
-    t0 = time.perf_counter()
-    oracle.pcg(coef, b, 0.0, 4)
-    t4 = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.pcg(coef, b, 0.0, 20)
-    t20 = time.perf_counter() - t0
-    per = max(1e-4, (t20 - t4) / 16)
-    setup = max(0.0, t4 - 4 * per)
-    k = max(3, int((budget_s - setup) / per))
-    t0 = time.perf_counter()
-    _, iters, _, _ = oracle.pcg(coef, b, 0.0, k)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
-    return {"value": iters / dt, "unit": "iter/s", "cores": cores, "kind": "oracle",
+
+    def timed(budget):
+        # a warm-up run, two short runs to size the sample (per-iteration time
+        # and the per-call setup), then a run of about `budget` seconds
+        oracle.pcg(coef, b, 0.0, 1)
+        t0 = time.perf_counter()
+        oracle.pcg(coef, b, 0.0, 2)
+        t2 = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.pcg(coef, b, 0.0, 6)
+        t6 = time.perf_counter() - t0
+        per = max(1e-4, (t6 - t2) / 4)
+        setup = max(0.0, t2 - 2 * per)
+        k = max(3, int((budget - setup) / per))
+        t0 = time.perf_counter()
+        _, iters, _, _ = oracle.pcg(coef, b, 0.0, k)
+        return iters, time.perf_counter() - t0
+
+    threads = oracle.set_threads(0)
+    iters, dt = timed(budget_s)
+    oracle.set_threads(1)
+    iters1, dt1 = timed(budget_s / 2)
+    oracle.set_threads(threads)
+    return {"value": iters / dt, "unit": "iter/s", "cores": threads, "kind": "oracle",
             "sample": f"{iters} FP64 Jacobi-PCG iterations of {w.describe()} (tol=0, fixed count), "
-                      f"{dt:.1f} s, OpenMP threads={cores}; assembly excluded"}
+                      f"{dt:.1f} s, OpenMP threads={threads}; assembly excluded",
+            "one_thread": {"value": iters1 / dt1, "unit": "iter/s", "cores": 1,
+                           "sample": f"{iters1} iterations, {dt1:.1f} s, OpenMP threads=1"},
+            "host": host_cpu()}
+
+
+def rocm_version():
+    try:
+        return open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        return None
+
+
+def stream_ceiling(torch, dev, n):
+    """Practical HBM ceilings of plain streaming kernels on vectors of n
+    doubles: a copy (1 read + 1 write) and addcmul (3 reads + 1 write),
+    timed with events on the current stream."""
+    a = torch.rand(n, dtype=torch.float64, device=dev)
+    b, c, d = torch.rand_like(a), torch.rand_like(a), torch.empty_like(a)
+
+    def timed(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    t_copy = timed(lambda: d.copy_(a))
+    t_acm = timed(lambda: torch.addcmul(a, b, c, out=d))
+    out = {"vector_bytes": 8 * n, "copy_gbs": round(16.0 * n / t_copy / 1e9, 1),
+           "addcmul_3r1w_gbs": round(32.0 * n / t_acm / 1e9, 1)}
+    del a, b, c, d
+    return out
+
+
+def golden_samples(name):
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}.json")
+    try:
+        return json.load(open(path))
+    except (OSError, ValueError):
+        return None
+
+
+def err_vs_samples(torch, d_phi, g):
+    """Max |Phi - Phi_oracle| / max |Phi_oracle| at the golden file's sampled indices."""
+    if not g or "phi" not in g:
+        return None
+    import numpy as np
+
+    idx = torch.tensor(g["indices"], dtype=torch.long, device=d_phi.device)
+    got = d_phi.reshape(-1)[idx].cpu().numpy()
+    return float(np.abs(got - np.array(g["phi"])).max() / g["phi_max_abs"])
 
 
 def percentile(xs, q):
@@ -315,6 +407,10 @@ def main():
                     help="bytes streamed per iteration by the batch (server default: 256 MiB; 0 = no limit)")
     ap.add_argument("--no-closed-wall", action="store_true", help="skip the closed-wall solve")
     ap.add_argument("--no-refined", action="store_true", help="skip the FP32-refined solves of the default run")
+    ap.add_argument("--no-line", action="store_true", help="skip the phi-line preconditioner solves")
+    ap.add_argument("--no-ceiling", action="store_true", help="skip the streaming-ceiling measurement")
+    ap.add_argument("--no-large", action="store_true", help="skip the fixed-count run on the large grid")
+    ap.add_argument("--large-workload", default="bipole_301x641x1281")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, *args.summarize_pmc)
@@ -427,7 +523,14 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(kern[dom]["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_name(stats, dom),
-                "alg_bytes_per_launch": kern[dom]["alg_bytes_per_launch"], "ms_per_launch": kern[dom]["ms"]}
+                "alg_bytes_per_launch": kern[dom]["alg_bytes_per_launch"], "ms_per_launch": kern[dom]["ms"],
+                "basis": f"{KERNEL_KEYS[dom][0]:g} N bytes per launch: what this kernel must move"}
+    if one_sweep:
+        # the same launch time on the textbook two-pass basis of one PCG
+        # iteration (64 N: read r, p, x and re-read p, r; write p, x, r), which
+        # is what an iteration costs without the one-sweep rearrangement
+        roofline["achieved_64N_basis"] = round(64.0 * w.n / (kern[dom]["ms"] * 1e-3) / 1e9, 1)
+        roofline["frac_64N_basis"] = round(roofline["achieved_64N_basis"] / HBM_PEAK_GBS, 4)
 
     result = {
         "metric": "PCG iters/s + HBM GB/s (% peak) at 151x301x601; FP32-refined vs FP64 solve s",
@@ -458,6 +561,8 @@ def main():
         "field": field,
         "relres_true": stats["relres_true"],
         "phi_l2": phi_norm,
+        "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi, golden_samples(w.name)),
+        "rocm": rocm_version(), "torch": torch.__version__,
     }
     if one_sweep:
         # the two-pass form of the same FP64 iteration, one solve, for comparison
@@ -486,6 +591,32 @@ def main():
         print(f"[bench] closed wall: {it3 / t3:.1f} it/s ({it3} iters)", file=sys.stderr, flush=True)
         cw.close()
         del d_phi_cw
+    if not args.no_line:
+        # the phi-line block preconditioner on the same grid and data: fewer
+        # iterations, 80 N bytes each (direction update on z, r/x update,
+        # line pass)
+        solver.set_preconditioner(pot3d.PC_PHI_LINE)
+        d_phi_l = torch.empty_like(d_phi)
+        stl, itl, rrl = solver.solve_device(d_br, d_phi_l, w.tol, maxit)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for q in range(max(1, args.steps)):
+            stl, itl, rrl = solver.solve_device(d_br, d_phi_l, w.tol, maxit)
+        torch.cuda.synchronize()
+        tl = (time.perf_counter() - t0) / max(1, args.steps)
+        sl = solver.stats()
+        result["phi_line"] = {
+            "solve_s": round(tl, 4), "speedup_vs_point_jacobi": round(result["fp64_solve_s"] / tl, 3),
+            "iters": itl, "iters_point_jacobi": result["config"]["iters_per_solve"],
+            "iters_per_s": round(itl / tl, 2), "loop_us_per_iter": round(sl["loop_ms"] * 1e3 / max(1, itl), 2),
+            "gbs_alg_80N": round(80.0 * w.n * itl / (sl["loop_ms"] * 1e-3) / 1e9, 1),
+            "status": pot3d.STATUS_NAMES.get(stl, stl), "relres_true": rrl,
+            "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi_l, golden_samples(w.name + "_phi_line")),
+            "max_rel_diff_vs_point_jacobi": float(torch.max(torch.abs(d_phi_l - d_phi)).item()
+                                                  / torch.max(torch.abs(d_phi)).item())}
+        print(f"[bench] phi-line: {tl:.3f} s/solve ({itl} iters)", file=sys.stderr, flush=True)
+        solver.set_preconditioner(pot3d.PC_JACOBI)
+        del d_phi_l
     if not args.no_refined:
         # FP32-refined solves of the same problem to the same FP64 residual
         phi64 = d_phi.clone()
@@ -503,16 +634,82 @@ def main():
         rs = solver.stats()
         diff = float(torch.max(torch.abs(d_phi - phi64)).item() / torch.max(torch.abs(phi64)).item())
         result["fp32_refined"] = {"solve_s": round(t_ref, 4), "speedup_vs_fp64": round(result["fp64_solve_s"] / t_ref, 3),
+                                  "mode": "reliable updates (the FP32 direction continues across FP64 residual "
+                                          "replacements), inner tol 0.1 (the library default for this mode)",
                                   "inner_iters": it, "outer": rs["outer"], "relres_true": rr,
                                   "status": pot3d.STATUS_NAMES.get(st, st),
+                                  "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi,
+                                                                                  golden_samples(w.name)),
                                   "max_rel_diff_vs_fp64_gpu": diff}
         print(f"[bench] refined: {t_ref:.3f} s/solve ({it} inner iters, {rs['outer']} outer)", file=sys.stderr,
               flush=True)
+        # the mixed-precision configuration as first stated: plain defect
+        # correction, each inner FP32 PCG restarted and run to 1e-5
+        solver.set_refinement_mode(pot3d.REFINE_RESTART)
+        solver.set_refinement(1e-5, 50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st5, it5, rr5 = solver.solve_device(d_br, d_phi, w.tol, maxit)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter() - t0
+        r5 = solver.stats()
+        result["fp32_refined"]["restart_inner_1e-5"] = {
+            "solve_s": round(t5, 4), "speedup_vs_fp64": round(result["fp64_solve_s"] / t5, 3), "inner_iters": it5,
+            "outer": r5["outer"], "relres_true": rr5, "status": pot3d.STATUS_NAMES.get(st5, st5),
+            "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi, golden_samples(w.name))}
+        print(f"[bench] refined, restarts at inner tol 1e-5: {t5:.3f} s ({it5} inner iters, {r5['outer']} outer)",
+              file=sys.stderr, flush=True)
+    solver.close()
+    del d_phi, d_br
+    torch.cuda.empty_cache()
+    if not args.no_ceiling:
+        # practical ceilings of plain streaming kernels, at this workload's
+        # vector size and at 2 GB per vector (nothing reused from the 256 MB
+        # memory-side cache)
+        result["stream_ceiling"] = [stream_ceiling(torch, dev, w.n), stream_ceiling(torch, dev, 1 << 28)]
+        torch.cuda.empty_cache()
+        print(f"[bench] streaming ceilings: {result['stream_ceiling']}", file=sys.stderr, flush=True)
+    if not args.no_large:
+        result["large_grid"] = large_grid_leg(torch, dev, args.large_workload)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, faces, br, args.cpu_budget)
-    solver.close()
     print(json.dumps(result), flush=True)
+
+
+def large_grid_leg(torch, dev, name):
+    """One GPU's share at its full shape (default 301 x 641 x 1281, 247M
+    unknowns, 2 GB per vector): a short fixed-count run (no stopping test
+    reached), its per-iteration loop time and the sweep kernel's launch time.
+    The surface data are the workload's dipole alone (5 cos theta): a
+    fixed-count iteration does the same work whatever the values, and the
+    2000-bipole map takes most of a minute to sample on the host."""
+    from paper_1709_01126_amd import Solver
+    from workloads import WORKLOADS, magnetograms
+
+    w = WORKLOADS[name]
+    faces = w.faces()
+    br = magnetograms.br_dipole(faces[1], faces[2], 5.0)
+    print(f"[bench] large grid {w.describe()}: N={w.n}", file=sys.stderr, flush=True)
+    with Solver(*faces, device=0) as s:
+        d_br = torch.from_numpy(br).to(dev)
+        d_phi = torch.empty((w.nr, w.nt, w.np), dtype=torch.float64, device=dev)
+        s.solve_device(d_br, d_phi, 0.0, 8)
+        k = 40
+        st, it, rr = s.solve_device(d_br, d_phi, 0.0, k)
+        stats = s.stats()
+        ms_sweep, _ = s.time_kernels(8)
+        del d_phi, d_br
+    loop_us = stats["loop_ms"] * 1e3 / max(1, it)
+    out = {"workload": w.describe(), "data": "dipole 5 cos(theta)", "n": w.n, "fixed_iters": it, "loop_us_per_iter": round(loop_us, 2),
+           "iters_per_s": round(1e6 / loop_us, 2),
+           "gbs_alg_per_iteration": round(stats["bytes_per_iter"] / (loop_us * 1e-6) / 1e9, 1),
+           "sweep_ms": round(ms_sweep, 4), "sweep_gbs_alg_48N": round(48.0 * w.n / (ms_sweep * 1e-3) / 1e9, 1),
+           "sweep_frac": round(48.0 * w.n / (ms_sweep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+           "launch": {k2: stats[k2] for k2 in ("sweep_rows", "chunk_s", "blocks_s", "pitch")}}
+    print(f"[bench] large grid: {json.dumps(out)}", file=sys.stderr, flush=True)
+    return out
 
 
 if __name__ == "__main__":
