@@ -70,6 +70,8 @@ def test_server_results_equal_single_solves(precision, form, monkeypatch):
     print(f"\n[serving] {'fp64' if precision == P.FP64 else 'refined'} form {form}: {len(reqs)} requests, 3 slots, "
           f"{stats['replays']} replays, peak active {peak}, cached contexts {stats['cached_contexts']}", flush=True)
     assert peak == 3
+    # iterations per replay: 2 x 16 sweeps in the one-sweep form, 16 pairs of passes in two
+    assert stats["graph_iters"] == (32 if form == "1" else 16)
     for (case, *_), (phi_a, st_a, it_a, rr_a), (phi_s, info) in zip(reqs, ref, out):
         assert info["done"] == 1 and info["status"] == st_a == P.OK, (label(case), info)
         assert info["iters"] == it_a, (label(case), info["iters"], it_a)
