@@ -292,6 +292,30 @@ int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
  */
 int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc);
 
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the FP64
+ * point-Jacobi solve of pot3d_create + pot3d_solve_device + pot3d_destroy in
+ * one call that allocates nothing.  It runs the same one-sweep kernels; every
+ * buffer beyond the arguments (metric tables, b layer, x, r, p, partial sums,
+ * scalars) lives in a fixed 96 MiB device array that the library holds on
+ * each GPU it runs on until the process ends.
+ *   faces, upper_bc  as in pot3d_create (host arrays, read during the call)
+ *   d_br    device, nt*np;  d_phi0 device, N or NULL;  d_phi device, N, out
+ *   stream  hipStream_t as void* (NULL: the null stream); the work runs on the
+ *           current device, and the call returns when it is done
+ *   tol, maxit, iters, relres_true  as in pot3d_solve_device
+ * Limits: nr, nt, np <= 4096, nr*nt <= 65536, and 40 bytes per padded cell
+ * plus the tables within 96 MiB (64 x 128 x 256 fits; 101 x 201 x 401 does
+ * not): POT3D_EINVAL, before any device work, beyond them.  Calls are
+ * serialized by a process-wide lock (the array is shared by every call on a
+ * GPU and keeps the last call's contents); each call clears what must start
+ * at zero.  Returns the solve status as pot3d_solve_device does.
+ */
+int pot3d_solve_noalloc(const double *r_faces, int nr, const double *t_faces, int nt, const double *p_faces, int np,
+                        int upper_bc, const double *d_br, const double *d_phi0, double *d_phi, void *stream,
+                        double tol, int maxit, int *iters, double *relres_true);
+
 /* Free the context and all of its device memory.  NULL is a no-op. */
 void pot3d_destroy(pot3d_ctx *ctx);
 

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpot3d.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kernels.hip", "api.hip", "server.hip"]
+SOURCES = ["kernels.hip", "api.hip", "server.hip", "noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

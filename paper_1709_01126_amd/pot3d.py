@@ -27,7 +27,8 @@ STATUS_NAMES = {OK: "OK", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE"
 
 EXPORTED = ("pot3d_create", "pot3d_solve", "pot3d_solve_device", "pot3d_apply_device", "pot3d_rhs_device",
             "pot3d_precondition_device", "pot3d_pole_values", "pot3d_field_device", "pot3d_get_stats", "pot3d_time_kernels", "pot3d_set_refinement",
-            "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_set_preconditioner", "pot3d_destroy",
+            "pot3d_set_refinement_mode", "pot3d_set_iteration", "pot3d_set_preconditioner", "pot3d_solve_noalloc",
+            "pot3d_destroy",
             "pot3d_last_error", "pot3d_version",
             "pot3d_server_create", "pot3d_server_submit", "pot3d_server_step", "pot3d_server_result",
             "pot3d_server_set_cache_budget", "pot3d_server_get_stats", "pot3d_server_destroy",
@@ -115,6 +116,9 @@ def load(path: str = LIB_PATH):
     lib.pot3d_set_iteration.restype = i
     lib.pot3d_set_preconditioner.argtypes = [vp, i]
     lib.pot3d_set_preconditioner.restype = i
+    lib.pot3d_solve_noalloc.argtypes = [d, i, d, i, d, i, i, vp, vp, vp, vp, ctypes.c_double, i,
+                                        ctypes.POINTER(i), d]
+    lib.pot3d_solve_noalloc.restype = i
     lib.pot3d_field_device.argtypes = [vp, vp, vp, vp, vp]
     lib.pot3d_field_device.restype = i
     lib.pot3d_destroy.argtypes = [vp]
@@ -303,6 +307,19 @@ def pot3d_set_iteration(ctx, iteration):
 
 def pot3d_set_preconditioner(ctx, pc):
     return load().pot3d_set_preconditioner(ctx, int(pc))
+
+
+def pot3d_solve_noalloc(r_faces, t_faces, p_faces, upper_bc, d_br, d_phi0, d_phi, stream, tol, maxit):
+    """The solve that allocates nothing, on raw device pointers (ints) as in
+    C: the caller guarantees nt*np and N elements.  Returns (status, iters,
+    relres_true)."""
+    rf, tf, pf = _f64(r_faces), _f64(t_faces), _f64(p_faces)
+    it = ctypes.c_int(0)
+    rr = ctypes.c_double(0.0)
+    st = load().pot3d_solve_noalloc(_dp(rf), rf.size - 1, _dp(tf), tf.size - 1, _dp(pf), pf.size - 1, int(upper_bc),
+                                    d_br, d_phi0, d_phi, stream, float(tol), int(maxit), ctypes.byref(it),
+                                    ctypes.byref(rr))
+    return st, it.value, rr.value
 
 
 def pot3d_field_device(ctx, d_br, d_bt, d_bp, stream=None):

@@ -230,3 +230,20 @@ def test_server_submit_rejects_wrong_sizes():
         P.pot3d_server_submit(None, rf, tf, pf, np.zeros(5), 1e-9, 100)
     with pytest.raises(ValueError, match="phi_out"):
         P.pot3d_server_submit(None, rf, tf, pf, np.zeros(6 * 8), 1e-9, 100, np.empty(3))
+
+
+def test_noalloc_rejects_invalid_arguments_before_device_work():
+    rf, tf, pf = good_faces()
+    st, _, _ = P.pot3d_solve_noalloc(rf, tf, pf, P.UPPER_SOURCE_SURFACE, None, None, 1, None, 1e-10, 10)
+    assert st == P.EINVAL
+    st, _, _ = P.pot3d_solve_noalloc(rf, tf, pf, P.UPPER_SOURCE_SURFACE, 1, None, 2, None, -1.0, 10)
+    assert st == P.EINVAL
+    st, _, _ = P.pot3d_solve_noalloc(rf, tf, pf, 7, 1, None, 2, None, 1e-10, 10)
+    assert st == P.EINVAL
+    bad = rf.copy()
+    bad[2] = bad[1]
+    st, _, _ = P.pot3d_solve_noalloc(bad, tf, pf, P.UPPER_SOURCE_SURFACE, 1, None, 2, None, 1e-10, 10)
+    assert st == P.EINVAL
+    big = grids.r_faces_stretched(5000)
+    st, _, _ = P.pot3d_solve_noalloc(big, tf, pf, P.UPPER_SOURCE_SURFACE, 1, None, 2, None, 1e-10, 10)
+    assert st == P.EINVAL and "no-allocation" in P.pot3d_last_error(None)
