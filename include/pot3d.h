@@ -336,6 +336,8 @@ const char *pot3d_version(void);
  *   2. admits queued requests, in order, while a slot is free, their device
  *      memory fits the budget, and the bytes that the active solves stream
  *      per iteration stay within the cache budget (or no solve is active);
+ *      a request that does not fit beside the active solves may be passed
+ *      by up to 8 later ones that do, then waits at the head;
  *   3. advances every active solve by a fixed number of PCG iterations
  *      (32 sweeps in the one-sweep form, 16 two-pass iterations otherwise;
  *      the form is POT3D_ITERATION's when the server is created, one sweep

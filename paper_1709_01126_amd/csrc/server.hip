@@ -12,9 +12,11 @@
 //      the 256 MB memory-side cache) -- or the server is idle.  Solves that
 //      run from the cache alone are thus not batched into ones that would
 //      stream from HBM, and bandwidth-bound solves, which batching cannot
-//      speed up, run alone.  Per-grid contexts (tables and vectors) are
-//      cached and reused; idle ones are evicted oldest first when the budget
-//      needs it;
+//      speed up, run alone.  A request that does not fit beside the running
+//      solves is passed over by later ones that do (small solves batch while
+//      a large one waits for the server to drain), at most kMaxOvertake
+//      times.  Per-grid contexts (tables and vectors) are cached and reused;
+//      idle ones are evicted oldest first when the budget needs it;
 //   3. queues one replay of a captured graph of m batched PCG iterations (in
 //      the one-sweep form, the default: 2m sweeps of one batched sweep and one
 //      finisher each; in the two-pass form m iterations of two batched passes
@@ -23,9 +25,12 @@
 //      memory maps workgroups to slots), and slots that have converged are
 //      masked by their own done flags.
 // A step queues its replay before it reads the statuses of the previous one,
-// so the device always has the next replay queued while the host decides.  A
-// slot that finished in replay k runs through replay k+1 as a no-op, and
-// retirement and admission are ordered after it on the same stream.
+// so in steps where no solve ends or starts the device has the next replay
+// queued while the host decides.  A step that retires or admits a request
+// waits for the stream (Phi out, the refined mode's outer check, the slot
+// tables), so the pipeline drains there.  A slot that finished in replay k
+// runs through replay k+1 as a no-op, and retirement and admission are
+// ordered after it on the same stream.
 // The graphs read the slot tables at run time, so requests join and leave
 // between replays without recapture; one graph is captured per launch width
 // (pair of widths in the two-pass form) the first time a batch needs it.
@@ -63,6 +68,7 @@ struct Request {
     double relres_true = 0.0;
     double t_submit = 0.0, t_admit = -1.0, t_done = -1.0;
     bool done = false;
+    int overtaken = 0;   // later requests admitted while this one waited for streaming budget
 };
 
 struct Slot {
@@ -91,6 +97,7 @@ struct Replay {
 };
 
 constexpr int kBlockAlign = 8;   // slot offsets keep the XCD of a workgroup unchanged
+constexpr int kMaxOvertake = 8;  // later requests that may pass one waiting for streaming budget
 
 int round_up(int v, int a) { return (v + a - 1) / a * a; }
 
@@ -686,13 +693,30 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
         }
     for (Slot &sl : sv->slots) {
         if (sl.active || sv->queue.empty()) continue;
-        Request *r = sv->queue.front();
+        // the first queued request, in arrival order, that fits the streaming
+        // budget beside the running solves; the ones it passes are counted, and
+        // one that has been passed kMaxOvertake times blocks the queue until it
+        // fits (at the latest when the server is idle)
+        size_t pick = sv->queue.size();
+        bool blocked = false;
+        for (size_t qi = 0; qi < sv->queue.size(); ++qi) {
+            const size_t sb_q = stream_bytes(sv, sv->queue[qi]);
+            if (running == 0 || sv->cache_budget == 0 || streaming + sb_q <= sv->cache_budget) {
+                pick = qi;
+                break;
+            }
+            if (sv->queue[qi]->overtaken >= kMaxOvertake) {
+                blocked = true;
+                break;
+            }
+        }
+        if (blocked || pick == sv->queue.size()) break;
+        Request *r = sv->queue[pick];
         const size_t sb = stream_bytes(sv, r);
-        if (running > 0 && sv->cache_budget > 0 && streaming + sb > sv->cache_budget) break;
         pot3d_ctx *c = nullptr;
         int rc = acquire_context(sv, r, &c);
         if (rc != POT3D_OK) {   // the request cannot run on this server
-            sv->queue.pop_front();
+            sv->queue.erase(sv->queue.begin() + (long)pick);
             r->status = rc;
             r->t_done = sv->now();
             r->done = true;
@@ -700,7 +724,8 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
             continue;
         }
         if (!c) break;   // wait for memory
-        sv->queue.pop_front();
+        for (size_t qi = 0; qi < pick; ++qi) sv->queue[qi]->overtaken += 1;
+        sv->queue.erase(sv->queue.begin() + (long)pick);
         changed = true;
         rc = admit(sv, sl, r, c);
         if (rc != POT3D_OK) return rc;

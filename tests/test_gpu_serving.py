@@ -169,3 +169,28 @@ def test_server_cache_budget():
         assert peak == want_peak, (budget, peak)
         for (phi_a, st_a, it_a, _), (phi_s, info) in zip(ref, out):
             assert info["status"] == st_a and info["iters"] == it_a and np.array_equal(phi_s, phi_a)
+
+
+def test_server_small_requests_pass_a_waiting_large_one():
+    """Streaming budget 250 kB: two 6x10x40 solves (96 kB each in the one-sweep
+    form) fit side by side, a 20x37x101 solve (3.1 MB) fits only alone.  Small
+    requests queued behind the large one are admitted before it, up to 8 of
+    them, then it waits at the head; every result is still bitwise the single
+    solve's."""
+    small, large = GRIDS[3], GRIDS[4]
+    reqs = requests([small, large] + [small] * 10)
+    ref = alone(reqs, P.FP64)
+    with P.Server(precision=P.FP64, max_slots=4) as sv:
+        sv.set_cache_budget(250e3)
+        ids = [sv.submit(rf, tf, pf, br, tol, maxit) for _, rf, tf, pf, br, tol, maxit in reqs]
+        for _ in range(100_000):
+            if sv.step()[2] == len(ids):
+                break
+        out = [sv.take(rid) for rid in ids]
+    t_admit = [o[1]["t_admit"] for o in out]
+    before = sum(t < t_admit[1] for t in t_admit[2:])
+    print(f"\n[serving] small requests admitted before the waiting large one: {before}", flush=True)
+    assert 1 <= before <= 8
+    assert all(t >= t_admit[1] for t in t_admit[2 + before:])
+    for (phi_a, st_a, it_a, _), (phi_s, info) in zip(ref, out):
+        assert info["status"] == st_a == P.OK and info["iters"] == it_a and np.array_equal(phi_s, phi_a)
