@@ -291,6 +291,74 @@ def serve_trace(server, reqs, arrivals, log):
     return done, time.perf_counter() - t0
 
 
+def serve_saturation(reqs, precision, slots, log, cache_budget=None):
+    """The same requests through back-to-back single solves (cached contexts,
+    host arrays, as the server takes them) and through the server with every
+    request queued at once.  Returns solves/s, latencies and whether every
+    served solve took the same iterations as alone."""
+    import numpy as np
+
+    from paper_1709_01126_amd import Server, Solver
+
+    solvers, service, seq = {}, [], []
+    for w, faces, br in reqs:
+        key = (w.nr, w.nt, w.np)
+        if key not in solvers:
+            solvers[key] = Solver(*faces, precision=precision)
+            solvers[key].solve(br, w.tol, 1_000_000)   # warm-up
+    for w, faces, br in reqs:
+        t = time.perf_counter()
+        _, st, it, rr = solvers[(w.nr, w.nt, w.np)].solve(br, w.tol, 1_000_000)
+        service.append(time.perf_counter() - t)
+        seq.append(it)
+    for sv in solvers.values():
+        sv.close()
+    k = len(reqs)
+    seq_lat = fifo_latencies([0.0] * k, service)
+    with Server(precision=precision, max_slots=slots) as server:
+        if cache_budget is not None:
+            server.set_cache_budget(cache_budget)
+        warm = []
+        for key in sorted({(w.nr, w.nt, w.np) for w, _, _ in reqs}):
+            warm.append(next(r for r in reqs if (r[0].nr, r[0].nt, r[0].np) == key))
+        serve_trace(server, warm, [0.0] * len(warm), lambda m: None)
+        res, span = serve_trace(server, reqs, [0.0] * k, lambda m: None)
+    lat = [r[0] for r in res]
+    out = {"requests": k, "sequential_solves_per_s": round(k / sum(service), 4),
+           "server_solves_per_s": round(k / span, 4),
+           "server_over_sequential": round(sum(service) / span, 3),
+           "server_p50_s": round(percentile(lat, 50), 4), "server_p99_s": round(percentile(lat, 99), 4),
+           "sequential_p50_s": round(percentile(seq_lat, 50), 4), "sequential_p99_s": round(percentile(seq_lat, 99), 4),
+           "iters_equal_alone": all(r[1] == s_ for r, s_ in zip(res, seq)),
+           "all_ok": all(r[2] == 0 for r in res), "max_relres_true": max(r[3] for r in res)}
+    log(f"[serve] {json.dumps(out)}")
+    return out
+
+
+def serve_leg(n_requests, slots, log):
+    """Bounded serving measurement for the default line: the first
+    n_requests of the mixed-size trace, all queued at once, FP64 and
+    FP32-refined."""
+    from paper_1709_01126_amd import FP32_REFINED, FP64
+    from workloads import configs
+
+    reqs = []
+    for q in range(n_requests):
+        w = configs.serve_request(q)
+        faces = w.faces()
+        reqs.append((w, faces, w.br(faces)))
+    sizes = {}
+    for w, _, _ in reqs:
+        sizes[f"{w.nr}x{w.nt}x{w.np}"] = sizes.get(f"{w.nr}x{w.nt}x{w.np}", 0) + 1
+    out = {"trace": f"first {n_requests} requests of the serving trace (sizes uniform over "
+                    f"{['x'.join(map(str, z)) for z in configs.SERVE_SIZES]}, 50..500 bipoles, tol 1e-9), "
+                    f"all queued at once", "sizes": sizes, "slots": slots}
+    for name, prec in (("fp64", FP64), ("fp32_refined", FP32_REFINED)):
+        log(f"[serve] {name}: {n_requests} requests at saturation")
+        out[name] = serve_saturation(reqs, prec, slots, log)
+    return out
+
+
 def serve_main(args):
     """Continuous-batching serving on the mixed-size request trace."""
     import numpy as np
@@ -379,6 +447,19 @@ def serve_main(args):
             }
             mode["server_stats"] = server.stats()
         result["modes"][name] = mode
+    # one size at a time, 8 requests each, all queued at once: where batching
+    # pays (small, cache-resident, latency-bound solves) and where it cannot
+    # (bandwidth-bound ones)
+    result["per_size"] = {}
+    for size in configs.SERVE_SIZES:
+        reqs_s = []
+        for q in range(8):
+            wq = configs.Workload(f"size_{size}_{q}", *size, 1e-9, 300 + q, "ratio3", "bipoles", nbip=100)
+            faces = wq.faces()
+            reqs_s.append((wq, faces, wq.br(faces)))
+        key = "x".join(map(str, size))
+        result["per_size"][key] = {name: serve_saturation(reqs_s, prec, args.serve_slots, log)
+                                   for name, prec in (("fp64", FP64), ("fp32_refined", FP32_REFINED))}
     result["value"] = result["modes"]["fp64"]["saturation"]["server"]["solves_per_s"]
     print(json.dumps(result), flush=True)
 
@@ -396,8 +477,9 @@ def main():
                     help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) of a --profile-kernels "
                          "run into profiles/traffic_<workload>.json and exit")
     ap.add_argument("--profile-kernels", action="store_true",
-                    help="short run for hardware counters: a few iterations, the two stencil kernels "
-                         "--kernel-reps times each, and one device copy of N doubles (counter calibration)")
+                    help="short run for hardware counters: a few iterations and --kernel-reps timed launches of "
+                         "the FP64 sweep and the two passes, a few phi-line iterations, the FP32 sweep, and one "
+                         "device copy of N doubles (counter calibration)")
     ap.add_argument("--serve", action="store_true",
                     help="continuous-batching serving benchmark on the mixed-size request trace (own JSON line)")
     ap.add_argument("--serve-requests", type=int, default=24)
@@ -411,6 +493,8 @@ def main():
     ap.add_argument("--no-ceiling", action="store_true", help="skip the streaming-ceiling measurement")
     ap.add_argument("--no-large", action="store_true", help="skip the fixed-count run on the large grid")
     ap.add_argument("--large-workload", default="bipole_301x641x1281")
+    ap.add_argument("--serve-leg", type=int, default=12,
+                    help="requests of the bounded serving measurement in the default line (0: skip)")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(args.workload, *args.summarize_pmc)
@@ -450,6 +534,13 @@ def main():
         solver.solve_device(d_br, d_phi, 0.0, 8)
         ms_p, ms_r = solver.time_kernels(args.kernel_reps)
         solver.set_iteration(pot3d.ITER_ONE_SWEEP)
+        # the phi-line preconditioner's passes, and the FP32 sweep of the refined mode
+        solver.set_preconditioner(pot3d.PC_PHI_LINE)
+        solver.solve_device(d_br, d_phi, 0.0, 8)
+        solver.set_preconditioner(pot3d.PC_JACOBI)
+        with Solver(*faces, precision=FP32_REFINED, device=0) as s32:
+            s32.solve_device(d_br, d_phi, 0.0, 8)
+            ms_s32, _ = s32.time_kernels(args.kernel_reps)
         # counter calibration: a device copy of N doubles whose source is not in
         # the 256 MB memory-side cache (a 1 GB fill runs in between)
         src = torch.ones(w.n, dtype=torch.float64, device=dev)
@@ -460,6 +551,7 @@ def main():
         torch.cuda.synchronize()
         del flush
         print(json.dumps({"profile_kernels": w.describe(), "sweep_ms": ms_s, "update_p_ms": ms_p, "update_r_ms": ms_r,
+                          "sweep_fp32_ms": ms_s32,
                           "copy_bytes_each_way": 8 * w.n, "launch": solver.stats()}), flush=True)
         solver.close()
         return
@@ -672,6 +764,9 @@ def main():
     if not args.no_large:
         result["large_grid"] = large_grid_leg(torch, dev, args.large_workload)
         torch.cuda.empty_cache()
+    if args.serve_leg > 0:
+        result["serving"] = serve_leg(args.serve_leg, args.serve_slots,
+                                      lambda m: print(m, file=sys.stderr, flush=True))
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(w, faces, br, args.cpu_budget)
