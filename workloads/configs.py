@@ -20,6 +20,9 @@ import numpy as np
 from . import grids, magnetograms
 
 
+_BR_CACHE: dict = {}
+
+
 @dataclass(frozen=True)
 class Workload:
     name: str
@@ -48,7 +51,14 @@ class Workload:
         if self.br_kind == "harmonics":
             return magnetograms.br_harmonics(tf, pf, self.lmax, self.seed)[0]
         if self.br_kind == "bipoles":
-            return magnetograms.br_bipoles(tf, pf, self.nbip, self.seed)
+            # large maps take tens of seconds to sample: keep one copy per
+            # workload for the process (a copy is returned)
+            key = (self.name, self.nbip, self.seed, tf.tobytes(), pf.tobytes())
+            if key not in _BR_CACHE:
+                if len(_BR_CACHE) >= 4:
+                    _BR_CACHE.clear()
+                _BR_CACHE[key] = magnetograms.br_bipoles(tf, pf, self.nbip, self.seed)
+            return _BR_CACHE[key].copy()
         if self.br_kind == "dipole":
             return magnetograms.br_dipole(tf, pf)
         raise ValueError(self.br_kind)
