@@ -751,6 +751,27 @@ def main():
             "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi, golden_samples(w.name))}
         print(f"[bench] refined, restarts at inner tol 1e-5: {t5:.3f} s ({it5} inner iters, {r5['outer']} outer)",
               file=sys.stderr, flush=True)
+        if not args.no_line:
+            # both directions at once: FP32 inner iterations with the phi-line
+            # preconditioner (reliable updates, the default inner tolerance)
+            solver.set_refinement_mode(pot3d.REFINE_RELIABLE)
+            solver.set_refinement(0.1, 50)
+            solver.set_preconditioner(pot3d.PC_PHI_LINE)
+            solver.solve_device(d_br, d_phi, w.tol, maxit)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for q in range(max(1, args.steps)):
+                stl, itl, rrl = solver.solve_device(d_br, d_phi, w.tol, maxit)
+            torch.cuda.synchronize()
+            tl = (time.perf_counter() - t0) / max(1, args.steps)
+            rl = solver.stats()
+            result["fp32_refined"]["phi_line"] = {
+                "solve_s": round(tl, 4), "speedup_vs_fp64": round(result["fp64_solve_s"] / tl, 3),
+                "inner_iters": itl, "outer": rl["outer"], "relres_true": rrl,
+                "status": pot3d.STATUS_NAMES.get(stl, stl),
+                "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi, golden_samples(w.name + "_phi_line"))}
+            print(f"[bench] refined with the phi-line preconditioner: {tl:.3f} s ({itl} inner iters, "
+                  f"{rl['outer']} outer)", file=sys.stderr, flush=True)
     solver.close()
     del d_phi, d_br
     torch.cuda.empty_cache()

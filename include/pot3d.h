@@ -112,8 +112,8 @@ typedef struct pot3d_stats {
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
     double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 48 N (FP64, one
                                 sweep), 64 N (FP64, two passes), 80 N (FP64, phi-line
-                                preconditioner), 24 N / 32 N (FP32 inner, one sweep / two
-                                passes)                                                    */
+                                preconditioner), 24 N / 32 N / 40 N (FP32 inner: one
+                                sweep / two passes / phi-line)                             */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -274,21 +274,24 @@ int pot3d_set_refinement_mode(pot3d_ctx *ctx, int mode);
 int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
 
 /*
- * Preconditioner of the context's FP64 solves (Sec. 2.3 uses point Jacobi;
- * Sec. 6 asks for stronger ones that still suit vector hardware):
+ * Preconditioner of the context's PCG iterations: the FP64 iterations of an
+ * FP64 context, or the FP32 inner iterations of an FP32-refined one (Sec. 2.3
+ * uses point Jacobi; Sec. 6 asks for stronger ones that still suit vector
+ * hardware):
  *   POT3D_PC_JACOBI    point Jacobi (default), either iteration form;
  *   POT3D_PC_PHI_LINE  phi-line blocks.  Each PCG iteration then runs the
  *                      direction update on z = M^-1 r, the r/x update, and a
  *                      line pass that solves the rows (one wavefront per row:
  *                      the circulant block of a uniform phi grid factors
- *                      into two first-order periodic recurrences) and writes
- *                      z: 80 bytes per unknown per iteration against 48 or 64
+ *                      into two first-order periodic recurrences, always
+ *                      evaluated in FP64) and writes z: 80 bytes per unknown
+ *                      per FP64 iteration (40 per FP32 one) against 48 or 64
  *                      for point Jacobi, for fewer iterations.  Allocates one
- *                      more vector (8 N bytes) on first use.
- * POT3D_EINVAL (nothing changed) unless ctx is an FP64 context whose phi
- * faces are uniform (every width 2 pi / np to 1e-12 relative) with
- * np <= 2048, or for another value of pc.  POT3D_ENOMEM / POT3D_EDEVICE if
- * the vector or the iteration graph cannot be made.
+ *                      more vector (8 N or 4 N bytes) on first use.
+ * POT3D_EINVAL (nothing changed) unless the context's phi faces are uniform
+ * (every width 2 pi / np to 1e-12 relative) with np <= 2048, or for another
+ * value of pc.  POT3D_ENOMEM / POT3D_EDEVICE if the vector or the iteration
+ * graph cannot be made.
  */
 int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc);
 

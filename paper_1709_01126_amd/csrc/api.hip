@@ -485,30 +485,37 @@ int capture_sweeps(pot3d_ctx *c, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *s
 // Capture m PCG iterations with the phi-line block preconditioner: the
 // direction update on z (p = z + beta p_old, A p, p.Ap), alpha, the r/x
 // update, the line pass (z = M^-1 r, r.z, r.r), then beta and convergence.
-int capture_line_iterations(pot3d_ctx *c, hipGraphExec_t *out)
+// V: the vector type (FP64 solves, or the FP32 inner iterations of the
+// refined mode, whose scalars and sums stay FP64).
+template <typename V>
+int capture_line_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, V *z, DevScalars *sc, hipGraphExec_t *out)
 {
     hipStream_t s = c->stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    double *pb[2] = {c->p[0], c->p[1]};
+    V *pb[2] = {p0, p1};
     for (int it = 0; it < c->graph_m && e == hipSuccess; ++it) {
-        StencilVecs<double> a = base_vecs(c);
-        a.in = c->z;
+        StencilVecs<V> a{};
+        a.sc = sc;
+        a.partial = c->partial;
+        a.in = z;
         a.pold = pb[it & 1];
         a.pnew = pb[(it + 1) & 1];
         a.zin = 1;
-        e = launch_stencil<double>(kUpdateP, c->tile_p, c->grid_p, a, s);
-        if (e == hipSuccess) e = launch_finish(kFinSigma, c->sc, c->partial, c->grid_p.nblocks, s);
+        e = launch_stencil<V>(kUpdateP, c->tile_p, c->grid_p, a, s);
+        if (e == hipSuccess) e = launch_finish(kFinSigma, sc, c->partial, c->grid_p.nblocks, s);
         if (e == hipSuccess) {
-            StencilVecs<double> bv = base_vecs(c);
+            StencilVecs<V> bv{};
+            bv.sc = sc;
+            bv.partial = c->partial;
             bv.in = pb[(it + 1) & 1];
-            bv.r = c->r;
-            bv.x = c->x;
+            bv.r = r;
+            bv.x = x;
             bv.zin = 1;
-            e = launch_stencil<double>(kUpdateR, c->tile_r, c->grid_r, bv, s);
+            e = launch_stencil<V>(kUpdateR, c->tile_r, c->grid_r, bv, s);
         }
-        if (e == hipSuccess) e = launch_line(c->grid_o, c->r, c->z, c->partial, c->line_blocks, c->sc, 0, s);
-        if (e == hipSuccess) e = launch_finish(kFinRho, c->sc, c->partial, c->line_blocks, s);
+        if (e == hipSuccess) e = launch_line<V>(c->grid_o, r, z, c->partial, c->line_blocks, sc, 0, s);
+        if (e == hipSuccess) e = launch_finish(kFinRho, sc, c->partial, c->line_blocks, s);
     }
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(s, &graph);
@@ -561,13 +568,14 @@ void free_ctx(pot3d_ctx *c)
     if (c->graph32) (void)hipGraphExecDestroy(c->graph32);
     if (c->graph_s) (void)hipGraphExecDestroy(c->graph_s);
     if (c->graph_l) (void)hipGraphExecDestroy(c->graph_l);
+    if (c->graph32l) (void)hipGraphExecDestroy(c->graph32l);
     if (c->graph32s) (void)hipGraphExecDestroy(c->graph32s);
     for (hipEvent_t *e : {&c->ev_poll[0], &c->ev_poll[1], &c->ev_t0, &c->ev_t1, &c->ev_loop0, &c->ev_loop1})
         if (*e) (void)hipEventDestroy(*e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
     void *bufs[] = {c->rows, c->dphi, c->ih, c->bfac, c->x, c->r, c->r2, c->p[0], c->p[1],
                     c->bplane, c->br, c->partial, c->poles, c->vr, c->vt, c->bcs, c->ftab, c->sc,
-                    c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32, c->z};
+                    c->r32, c->r32b, c->p32[0], c->p32[1], c->e32, c->sc32, c->z, c->z32};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -640,7 +648,7 @@ int start_fp64(pot3d_ctx *c, hipStream_t s, double tol, int maxit)
     if (c->precond == POT3D_PC_PHI_LINE) {
         // z = M^-1 r of the starting residual and rho = r.z (the first
         // direction update then forms p = z)
-        HIP_TRY(c, launch_line(c->grid_o, c->r, c->z, c->partial, c->line_blocks, c->sc, 1, s));
+        HIP_TRY(c, launch_line<double>(c->grid_o, c->r, c->z, c->partial, c->line_blocks, c->sc, 1, s));
         HIP_TRY(c, launch_finish(kFinLineInit, c->sc, c->partial, c->line_blocks, s));
     }
     return POT3D_OK;
@@ -730,6 +738,12 @@ int refined_start_inner(pot3d_ctx *c, hipStream_t s, double tol, int maxit_left,
     }
     c->h_sc[1] = in;
     HIP_TRY(c, hipMemcpyAsync(c->sc32, &c->h_sc[1], sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    if (c->precond == POT3D_PC_PHI_LINE) {
+        // z = M^-1 r of the new FP32 residual, with r.z and r.r
+        HIP_TRY(c, launch_line<float>(c->grid_o, c->r32, c->z32, c->partial, c->line_blocks, c->sc32, 1, s));
+        HIP_TRY(c, launch_finish(resume ? kFinResume : kFinInner, c->sc32, c->partial, c->line_blocks, s));
+        return POT3D_OK;
+    }
     HIP_TRY(c, launch_dots_rz(c->grid_o, c->r32, c->partial, nb_dots, s));
     HIP_TRY(c, launch_finish(resume ? kFinResume : kFinInner, c->sc32, c->partial, nb_dots, s));
     return POT3D_OK;
@@ -769,8 +783,9 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         rc = refined_start_inner(c, s, tol, maxit - total, out, outer > 0 ? &inner : nullptr, scale_prev);
         if (rc != POT3D_OK) return rc;
         scale_prev = out.scale;
-        const bool sweep = one_sweep(c);
-        rc = replay_until_done(c, sweep ? c->graph32s : c->graph32, c->sc32, s, maxit - total,
+        const bool line = c->precond == POT3D_PC_PHI_LINE;
+        const bool sweep = !line && one_sweep(c);
+        rc = replay_until_done(c, line ? c->graph32l : (sweep ? c->graph32s : c->graph32), c->sc32, s, maxit - total,
                                sweep ? 2 * c->graph_m : c->graph_m, &launches, &inner);
         if (rc != POT3D_OK) return rc;
         total += inner.k;
@@ -783,8 +798,8 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         if (rc != POT3D_OK) return rc;
     }
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, one_sweep(c) ? 24.0 : 32.0, iters,
-                        relres_true);
+    const double per = c->precond == POT3D_PC_PHI_LINE ? 40.0 : (one_sweep(c) ? 24.0 : 32.0);
+    return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, per, iters, relres_true);
 }
 
 // The solve proper.  br_dev: device Br (nt*np); phi0: initial guess or NULL
@@ -1291,7 +1306,7 @@ int pot3d_precondition_device(pot3d_ctx *ctx, const double *d_r, double *d_z, vo
     double *zpad = ctx->p[1];
     if (ctx->precond == POT3D_PC_PHI_LINE) {
         zpad = ctx->z;
-        HIP_TRY(ctx, launch_line(ctx->grid_o, ctx->r, zpad, ctx->partial, ctx->line_blocks, ctx->sc, 1, s));
+        HIP_TRY(ctx, launch_line<double>(ctx->grid_o, ctx->r, zpad, ctx->partial, ctx->line_blocks, ctx->sc, 1, s));
     } else {
         HIP_TRY(ctx, launch_jacobi(ctx->grid_o, ctx->r, zpad, s));
     }
@@ -1359,7 +1374,7 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     out->pitch = ctx->pitch;
     fill_shape(ctx, *out);
     const bool fp32 = ctx->precision == POT3D_FP32_REFINED;
-    const double per = ctx->precond == POT3D_PC_PHI_LINE ? 80.0
+    const double per = ctx->precond == POT3D_PC_PHI_LINE ? (fp32 ? 40.0 : 80.0)
                        : one_sweep(ctx) ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0);
     out->bytes_per_iter = per * (double)ctx->n;
     return POT3D_OK;
@@ -1413,8 +1428,7 @@ int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc)
         ctx->precond = pc;
         return POT3D_OK;
     }
-    if (ctx->precision != POT3D_FP64 || ctx->serving)
-        return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner runs FP64 single solves only");
+    if (ctx->serving) return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner runs single solves only");
     if (ctx->np > kMaxLineCells)
         return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner takes at most 2048 azimuthal cells");
     const double h = kTwoPi / ctx->np;
@@ -1423,16 +1437,31 @@ int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc)
             return fail(ctx, POT3D_EINVAL, "the phi-line preconditioner needs uniform phi faces");
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
-    if (!ctx->z) {
-        HIP_TRY(ctx, dalloc(&ctx->z, (size_t)ctx->npad));
-        HIP_TRY(ctx, launch_fill<double>(ctx->z, ctx->npad, 0.0, ctx->stream));
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-    }
-    if (!ctx->graph_l) {
-        const long long rows = (long long)ctx->nr * ctx->nt;
-        ctx->line_blocks = (int)std::max<long long>(1, std::min<long long>((rows + kWaves - 1) / kWaves, ctx->max_blocks));
-        const int rc = capture_line_iterations(ctx, &ctx->graph_l);
-        if (rc != POT3D_OK) return rc;
+    const long long rows = (long long)ctx->nr * ctx->nt;
+    ctx->line_blocks = (int)std::max<long long>(1, std::min<long long>((rows + kWaves - 1) / kWaves, ctx->max_blocks));
+    if (ctx->precision == POT3D_FP64) {
+        if (!ctx->z) {
+            HIP_TRY(ctx, dalloc(&ctx->z, (size_t)ctx->npad));
+            HIP_TRY(ctx, launch_fill<double>(ctx->z, ctx->npad, 0.0, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        if (!ctx->graph_l) {
+            const int rc = capture_line_iterations<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->z, ctx->sc,
+                                                           &ctx->graph_l);
+            if (rc != POT3D_OK) return rc;
+        }
+    } else {
+        // FP32-refined: the inner FP32 iterations take the line preconditioner
+        if (!ctx->z32) {
+            HIP_TRY(ctx, dalloc(&ctx->z32, (size_t)ctx->npad));
+            HIP_TRY(ctx, launch_fill<float>(ctx->z32, ctx->npad, 0.0f, ctx->stream));
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        }
+        if (!ctx->graph32l) {
+            const int rc = capture_line_iterations<float>(ctx, ctx->r32, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->z32,
+                                                          ctx->sc32, &ctx->graph32l);
+            if (rc != POT3D_OK) return rc;
+        }
     }
     ctx->precond = pc;
     return POT3D_OK;

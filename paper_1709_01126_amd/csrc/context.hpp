@@ -72,12 +72,14 @@ struct pot3d_ctx {
     hipGraphExec_t graph_s = nullptr;     // FP64 sweeps
     hipGraphExec_t graph32s = nullptr;    // FP32 inner sweeps
 
-    // Preconditioner of FP64 single solves: point Jacobi (PC1) or the phi-line
-    // blocks, which iterate in two passes plus a line pass that writes z.
+    // Preconditioner of single solves (the FP64 iterations, or the FP32 inner
+    // ones of the refined mode): point Jacobi (PC1) or the phi-line blocks,
+    // which iterate in two passes plus a line pass that writes z.
     int precond = POT3D_PC_JACOBI;
     double *z = nullptr;          // phi-line: z = M^-1 r
+    float *z32 = nullptr;         // ... of the FP32 inner iterations (refined mode)
     int line_blocks = 0;          // workgroups of a line pass
-    hipGraphExec_t graph_l = nullptr;
+    hipGraphExec_t graph_l = nullptr, graph32l = nullptr;
 
     bool serving = false;         // a batching-server slot: iterates in the server's graph, captures none
     bool have_solution = false;

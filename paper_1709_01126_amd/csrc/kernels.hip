@@ -1463,17 +1463,19 @@ __device__ __forceinline__ double block_recurrence(double x, double &carry, cons
     }
 }
 
-// NB = blocks of 64 cells per row (np in (64 (NB - 1), 64 NB]).
-template <int NB>
+// NB = blocks of 64 cells per row (np in (64 (NB - 1), 64 NB]).  V is the
+// storage type of r and z (FP64, or FP32 for the inner iterations of the
+// refined mode); the recurrences always run in FP64.
+template <int NB, typename V>
 __global__ void __launch_bounds__(kThreads)
-line_solve_kernel(GridArgs g, const double *__restrict__ rin, double *__restrict__ zout, double *__restrict__ partial,
+line_solve_kernel(GridArgs g, const V *__restrict__ rin, V *__restrict__ zout, double *__restrict__ partial,
                   const DevScalars *__restrict__ sc, int ignore_done)
 {
     const CPtr<const DevScalars> csc = to_const(sc);
     if (!ignore_done && csc->done) return;   // uniform over the workgroup
     __shared__ double red[kWaves][2];
-    const GPtr<const double> gr = to_global(rin);
-    const GPtr<double> gz = to_global(zout);
+    const GPtr<const V> gr = to_global(rin);
+    const GPtr<V> gz = to_global(zout);
     const CPtr<const RowCoef> crows = to_const(g.rows);
     const int np = g.np;
     const int lane = threadIdx.x & (kWave - 1);
@@ -1493,7 +1495,7 @@ line_solve_kernel(GridArgs g, const double *__restrict__ rin, double *__restrict
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int k = q * kWave + lane;
-            rv[q] = (q < NB - 1 || lane_last) ? stream_load(gr + CHK(base + k, g.npad)) : 0.0;
+            rv[q] = (q < NB - 1 || lane_last) ? (double)stream_load(gr + CHK(base + k, g.npad)) : 0.0;
         }
         const double wgt = rc.pq * ih;                       // azimuthal weight w
         const double e = dph * rc.s / (2.0 * wgt);           // d / (2 w) - 1 > 0
@@ -1544,7 +1546,7 @@ line_solve_kernel(GridArgs g, const double *__restrict__ rin, double *__restrict
             }
             if (q < NB - 1 || lane_last) {
                 const double z = scale * __builtin_fma(fe, v0, u[q]);
-                stream_store(gz + CHK(base + k, g.npad), z);
+                stream_store(gz + CHK(base + k, g.npad), (V)z);
                 acc_rz = __builtin_fma(rv[q], z, acc_rz);
                 acc_rr = __builtin_fma(rv[q], rv[q], acc_rr);
             }
@@ -1593,24 +1595,29 @@ hipError_t launch_jacobi(const GridArgs &g, const double *r, double *z, hipStrea
     return hipGetLastError();
 }
 
-template <int NB>
-static hipError_t launch_line_nb(int nb, const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
+template <int NB, typename V>
+static hipError_t launch_line_nb(int nb, const GridArgs &g, const V *r, V *z, double *partial, int nblocks,
                                  const DevScalars *sc, int ignore_done, hipStream_t s)
 {
     if constexpr (NB > 1) {
-        if (nb < NB) return launch_line_nb<NB - 1>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
+        if (nb < NB) return launch_line_nb<NB - 1, V>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
     }
-    line_solve_kernel<NB><<<nblocks, kThreads, 0, s>>>(g, r, z, partial, sc, ignore_done);
+    line_solve_kernel<NB, V><<<nblocks, kThreads, 0, s>>>(g, r, z, partial, sc, ignore_done);
     return hipGetLastError();
 }
 
-hipError_t launch_line(const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
-                       const DevScalars *sc, int ignore_done, hipStream_t s)
+template <typename V>
+hipError_t launch_line(const GridArgs &g, const V *r, V *z, double *partial, int nblocks, const DevScalars *sc,
+                       int ignore_done, hipStream_t s)
 {
     const int nb = (g.np + kWave - 1) / kWave;
     if (nb < 1 || nb > kMaxLineCells / kWave) return hipErrorInvalidValue;
-    return launch_line_nb<kMaxLineCells / kWave>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
+    return launch_line_nb<kMaxLineCells / kWave, V>(nb, g, r, z, partial, nblocks, sc, ignore_done, s);
 }
+template hipError_t launch_line<double>(const GridArgs &, const double *, double *, double *, int,
+                                        const DevScalars *, int, hipStream_t);
+template hipError_t launch_line<float>(const GridArgs &, const float *, float *, double *, int, const DevScalars *,
+                                       int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Refinement helpers (pointwise over the padded arrays; padding stays zero).

@@ -85,10 +85,12 @@ hipError_t launch_gauge(double *x, const double *vr, const double *vt, const dou
                         int pitch, double inv_volume, double *partial, int nblocks, double *mean, hipStream_t s);
 
 // phi-line block preconditioner (uniform phi, np <= kMaxLineCells): z = M^-1 r
-// row by row, partial sums [0][b] = r.z and [1][b] = r.r for b < nblocks.
+// row by row (r and z stored as V, the recurrences in FP64), partial sums
+// [0][b] = r.z and [1][b] = r.r for b < nblocks.
 constexpr int kMaxLineCells = 32 * 64;
-hipError_t launch_line(const GridArgs &g, const double *r, double *z, double *partial, int nblocks,
-                       const DevScalars *sc, int ignore_done, hipStream_t s);
+template <typename V>
+hipError_t launch_line(const GridArgs &g, const V *r, V *z, double *partial, int nblocks, const DevScalars *sc,
+                       int ignore_done, hipStream_t s);
 
 // Point Jacobi z = D^-1 r (padded layout).
 hipError_t launch_jacobi(const GridArgs &g, const double *r, double *z, hipStream_t s);

@@ -176,5 +176,73 @@ def test_line_preconditioner_rejects_what_it_cannot_run():
             s.set_preconditioner(7)
     rf, tf, pf = make_faces(4, 6, 8, "stretched", "ratio3", "uniform")
     with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        s.set_preconditioner(P.PC_PHI_LINE)   # the FP32 inner iterations take it
+        z = torch.empty((4, 6, 8), dtype=torch.float64, device="cuda:0")
         with pytest.raises(P.Pot3dError, match="FP64"):
-            s.set_preconditioner(P.PC_PHI_LINE)
+            s.precondition(z.clone(), z)     # the entry point itself is FP64 only
+
+
+def test_full_size_bipole_151x301x601_phi_line():
+    """The benchmark workload with the phi-line preconditioner against the
+    oracle's line-preconditioned solve (tests/golden/make_oracle_samples.py
+    --precond phi_line): fixed-count iterates, converged Phi at the sampled
+    indices and through the per-layer functionals, iteration count, true
+    residual recomputed with the oracle's operator."""
+    import json
+    import os
+
+    from test_gpu_parity import GOLDEN_DIR, check_layer_functionals
+    from workloads import WORKLOADS
+
+    path = os.path.join(GOLDEN_DIR, "oracle_bipole_151x301x601_phi_line.json")
+    if not os.path.exists(path):
+        pytest.skip("no line-preconditioned oracle samples")
+    g = json.load(open(path))
+    w = WORKLOADS[g["workload"]]
+    rf, tf, pf = w.faces()
+    br = w.br((rf, tf, pf))
+    idx = np.array(g["indices"])
+    with line_solver(rf, tf, pf) as s:
+        for K, ref in g["fixed"].items():
+            phik, st, it, _ = gpu_solve(s, br, 0.0, int(K))
+            assert st == P.ENOCONV and it == int(K)
+            err = np.abs(phik.ravel()[idx] - np.array(ref["phi"])).max() / ref["phi_max_abs"]
+            print(f"[line full size] fixed K={K}: max rel diff {err:.2e}", flush=True)
+            assert err <= 1e-11, (K, err)
+        phi, st, it, rr = gpu_solve(s, br, w.tol, 200_000)
+    print(f"[line full size] gpu iters {it} (oracle {g['iters']}) true_relres {rr:.3e}", flush=True)
+    assert st == P.OK and g["status"] == oracle.OK
+    assert iters_close(it, g["iters"]), (it, g["iters"])
+    err = np.abs(phi.ravel()[idx] - np.array(g["phi"])).max() / g["phi_max_abs"]
+    assert err <= 1e-8, err
+    check_layer_functionals(phi, g, 1e-8)
+    coef = oracle.assemble(rf, tf, pf)
+    b = oracle.rhs(rf, tf, pf, br)
+    tr = oracle.true_relres(coef, b, phi)
+    assert abs(tr - rr) <= 1e-2 * tr + 1e-13
+    assert tr <= 1.5 * w.tol
+
+
+@pytest.mark.parametrize("case", [LINE_GRIDS[5], LINE_GRIDS[7]], ids=label)
+def test_refined_with_line_preconditioner(case):
+    """FP32-refined mode with the phi-line preconditioner on its FP32 inner
+    iterations: the FP64 true residual (recomputed by the oracle) meets tol,
+    Phi agrees with the oracle's FP64 line-preconditioned solve to 1e-7 (two
+    tol-accurate answers), and the inner iterations stay near the FP64 line
+    iteration count."""
+    rf, tf, pf = make_faces(*case)
+    br, _ = magnetograms.br_harmonics(tf, pf, 4, seed=2)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000, precond="phi_line")
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED) as s:
+        s.set_preconditioner(P.PC_PHI_LINE)
+        phi, st, it, rr = gpu_solve(s, br, tol, 100_000)
+        stats = s.stats()
+    tr = oracle.true_relres(ref["coef"], ref["b"], phi)
+    err = np.linalg.norm(phi - ref["phi"]) / np.linalg.norm(ref["phi"])
+    print(f"[line refined] {label(case)}: {it} inner iterations in {stats['outer']} outer (FP64 line "
+          f"{ref['iters']}), true relres {tr:.2e}, rel err {err:.2e}", flush=True)
+    assert st == P.OK and tr <= tol * 1.01
+    assert stats["bytes_per_iter"] == 40.0 * phi.size
+    assert err <= 1e-7
+    assert it <= 2 * ref["iters"] + 64

@@ -370,12 +370,16 @@ def test_full_size_bipole_151x301x601():
 
 def test_full_size_bipole_301x641x1281():
     """One GPU's share at 301 x 641 x 1281 (247M unknowns, 2 GB per vector).
-    The oracle's fixed-count iterates (K = 5, 20) at sampled indices, written
-    by tests/golden/make_oracle_samples.py --fixed-only, must match to 1e-12
-    as at 151 x 301 x 601.  A full solve is too long for the oracle here, so
-    the converged GPU solution is checked by a property that holds at any
-    size: its true residual, recomputed with the oracle's own operator, meets
-    the workload's tolerance and matches the residual the library reports."""
+    The oracle's fixed-count iterates (K = 5, 20) at sampled indices must
+    match to 1e-12 as at 151 x 301 x 601.  The converged GPU solution is
+    checked against the oracle's converged solve (written by
+    tests/golden/make_oracle_samples.py, several hours of CPU) where the golden
+    file holds it: the sampled values and the per-layer functionals to 1e-8 of
+    ||Phi|| (the 2-norm bar at tol 1e-9 on this grid: two CG codes stop at
+    slightly different iterates), and the iteration count within 0.5 %; and by
+    a property that holds at any size: its true residual, recomputed with the
+    oracle's own operator, meets the workload's tolerance and matches the
+    residual the library reports."""
     g = _golden("bipole_301x641x1281")
     w = WORKLOADS[g["workload"]]
     rf, tf, pf = w.faces()
@@ -394,6 +398,14 @@ def test_full_size_bipole_301x641x1281():
         stats = s.stats()
     print(f"[full size] gpu iters {it} true_relres {rr:.3e} solve {stats['solve_ms'] / 1e3:.1f} s", flush=True)
     assert st == P.OK and rr <= w.tol * 1.01
+    if "phi" in g:
+        print(f"[full size] oracle iters {g['iters']}", flush=True)
+        assert g["status"] == oracle.OK
+        assert iters_close(it, g["iters"]), (it, g["iters"])
+        err = np.abs(phi.ravel()[idx] - np.array(g["phi"])).max() / g["phi_max_abs"]
+        print(f"[full size] converged: sampled max rel diff {err:.2e}", flush=True)
+        assert err <= 1e-8, err
+        check_layer_functionals(phi, g, 1e-8)
     coef = oracle.assemble(rf, tf, pf)
     b = oracle.rhs(rf, tf, pf, br)
     tr = oracle.true_relres(coef, b, phi)
