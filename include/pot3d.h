@@ -79,8 +79,11 @@ enum pot3d_iteration {
     POT3D_ITER_ONE_SWEEP = 1   /* one sweep per iteration: the r/x update of iteration j-1
                                   and the direction update of iteration j together, with
                                   r.z of the next residual predicted from p.Ap, z.Ap and
-                                  Ap.D^-1 Ap (48 bytes per unknown in FP64, 24 in FP32).  The
-                                  same PCG in exact arithmetic.  Default.                   */
+                                  Ap.D^-1 Ap.  x is updated once per pair of sweeps, the
+                                  earlier increment rebuilt from p and z: 40 bytes per
+                                  unknown per iteration in FP64, 20 in FP32 (48 and 24
+                                  with POT3D_SWEEP_X=1 in the environment, x every sweep).
+                                  The same PCG in exact arithmetic.  Default.               */
 };
 
 enum pot3d_preconditioner {
@@ -110,10 +113,11 @@ typedef struct pot3d_stats {
     double relres_true;      /* ||b - A Phi||/||b||, recomputed in FP64 at exit             */
     double solve_ms;         /* wall time of the last solve call on the device             */
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
-    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 48 N (FP64, one
-                                sweep), 64 N (FP64, two passes), 80 N (FP64, phi-line
-                                preconditioner), 24 N / 32 N / 40 N (FP32 inner: one
-                                sweep / two passes / phi-line)                             */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 40 N (FP64, one
+                                sweep, x every other sweep; 48 N with x every sweep), 64 N
+                                (FP64, two passes), 80 N (FP64, phi-line preconditioner),
+                                20 N (24 N) / 32 N / 40 N (FP32 inner: one sweep / two
+                                passes / phi-line)                                         */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -229,9 +233,12 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out);
  * in the second replay each stencil launch records its first workgroup's
  * start and its last workgroup's end on the device wall clock.
  * Two-pass iteration: *ms_update_p = the p update (A p, p.Ap), *ms_update_r =
- * the r/x update (r.z, r.r).  One-sweep iteration: *ms_update_p = the sweep,
- * *ms_update_r = 0.  FP32-refined contexts time the FP32 inner kernels.  It runs on the vectors the context holds and overwrites them; a
- * later solve re-initializes everything.
+ * the r/x update (r.z, r.r).  One-sweep iteration: *ms_update_p = the even
+ * sweeps (x left to the next sweep), *ms_update_r = the odd sweeps (x of the
+ * pair); with POT3D_SWEEP_X=1 both time the sweep that updates x every time.
+ * FP32-refined contexts time the FP32 inner kernels.  It runs on the vectors
+ * the context holds and overwrites them; a later solve re-initializes
+ * everything.
  */
 int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms_update_r);
 
@@ -285,7 +292,7 @@ int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
  *                      the circulant block of a uniform phi grid factors
  *                      into two first-order periodic recurrences, always
  *                      evaluated in FP64) and writes z: 80 bytes per unknown
- *                      per FP64 iteration (40 per FP32 one) against 48 or 64
+ *                      per FP64 iteration (40 per FP32 one) against 40 or 64
  *                      for point Jacobi, for fewer iterations.  Allocates one
  *                      more vector (8 N or 4 N bytes) on first use.
  * POT3D_EINVAL (nothing changed) unless the context's phi faces are uniform

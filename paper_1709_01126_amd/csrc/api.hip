@@ -446,9 +446,28 @@ int capture_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, DevScalars *sc, h
     return POT3D_OK;
 }
 
+// x update of the one-sweep iteration for sweep `it` of a graph (even count,
+// starting at an even sweep): once per pair of sweeps by default,
+// POT3D_SWEEP_X=1 for every sweep.
+int sweep_xmode(int it)
+{
+    if (env_int("POT3D_SWEEP_X", 2) == 1) return 0;
+    return (it & 1) ? 2 : 1;
+}
+
+// HBM bytes per unknown per iteration of the one-sweep form: read r, p_old
+// and write r, p in every sweep, read and write x in every other one
+// (every one with POT3D_SWEEP_X=1).
+double sweep_bytes(bool fp32)
+{
+    const double b = env_int("POT3D_SWEEP_X", 2) == 1 ? 48.0 : 40.0;
+    return fp32 ? b / 2 : b;
+}
+
 // Capture 2 m sweeps of the one-sweep iteration (sweep, finisher) on the
 // idle context stream.  Sweep j reads r and p from buffer j mod 2 and writes
-// buffer (j + 1) mod 2; 2 m is even, so replays continue the alternation.
+// buffer (j + 1) mod 2; 2 m is even, so replays continue the alternation,
+// and of the x pairing too (an even sweep leaves x to the odd one after it).
 template <typename V>
 int capture_sweeps(pot3d_ctx *c, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc, hipGraphExec_t *out)
 {
@@ -466,6 +485,7 @@ int capture_sweeps(pot3d_ctx *c, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *s
         v.x = x;
         v.sc = sc;
         v.partial = c->partial;
+        v.xmode = sweep_xmode(it);
         e = launch_sweep<V>(c->sweep_rows, c->grid_s, v, s);
         if (e == hipSuccess) e = launch_finish(kFinSweep, sc, c->partial, c->grid_s.nblocks, s);
     }
@@ -669,8 +689,10 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     hipGraphExec_t graph = line ? c->graph_l : (sweep ? c->graph_s : c->graph);
     rc = replay_until_done(c, graph, c->sc, s, maxit, sweep ? 2 * c->graph_m : c->graph_m, &launches, &fin);
     if (rc != POT3D_OK) return rc;
+    // the increment of x the last sweep may have left to a next one
+    if (sweep) HIP_TRY(c, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, s));
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, line ? 80.0 : (sweep ? 48.0 : 64.0), iters,
+    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, line ? 80.0 : (sweep ? sweep_bytes(false) : 64.0), iters,
                         relres_true);
 }
 
@@ -788,6 +810,7 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         rc = replay_until_done(c, line ? c->graph32l : (sweep ? c->graph32s : c->graph32), c->sc32, s, maxit - total,
                                sweep ? 2 * c->graph_m : c->graph_m, &launches, &inner);
         if (rc != POT3D_OK) return rc;
+        if (sweep) HIP_TRY(c, launch_x_catchup<float>(c->e32, c->sc32, c->nr, c->nt, c->np, c->pitch, s));
         total += inner.k;
         ++outer;
         if (inner.status == POT3D_EBREAKDOWN) {
@@ -798,7 +821,7 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         if (rc != POT3D_OK) return rc;
     }
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    const double per = c->precond == POT3D_PC_PHI_LINE ? 40.0 : (one_sweep(c) ? 24.0 : 32.0);
+    const double per = c->precond == POT3D_PC_PHI_LINE ? 40.0 : (one_sweep(c) ? sweep_bytes(true) : 32.0);
     return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, per, iters, relres_true);
 }
 
@@ -977,9 +1000,11 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
 
 // Average duration of the one-sweep kernel as it runs in a solve: as
 // time_pair, with a graph of `reps` sweeps (sweep, finisher) of a fixed-count
-// FP64 PCG from x = 0 on the context's right-hand side.
+// FP64 PCG from x = 0 on the context's right-hand side.  ms_even, ms_odd: the
+// even sweeps (x left to the next sweep) and the odd ones (x of the pair).
 template <typename V>
-int time_sweeps(pot3d_ctx *ctx, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_sweep)
+int time_sweeps(pot3d_ctx *ctx, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_even,
+                double *ms_odd)
 {
     hipStream_t s = ctx->stream;
     const int m = std::max(2, reps + (reps & 1));   // even: the buffers alternate across the two replays
@@ -1022,6 +1047,7 @@ int time_sweeps(pot3d_ctx *ctx, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc
         v.partial = ctx->partial;
         v.ignore_done = 1;
         v.tstamp = d_ts + 2 * it;
+        v.xmode = sweep_xmode(it);
         e = launch_sweep<V>(ctx->sweep_rows, ctx->grid_s, v, s);
         if (e == hipSuccess) e = launch_finish(kFinSweep, sc, ctx->partial, ctx->grid_s.nblocks, s);
     }
@@ -1046,12 +1072,14 @@ int time_sweeps(pot3d_ctx *ctx, V *r0, V *r1, V *p0, V *p1, V *x, DevScalars *sc
     (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device);
     const double span_ticks = (double)(stamps[2 * (size_t)(m - 1) + 1] - stamps[0]);
     const double ms_per_tick = (span_ticks > 0.0 && span_ms > 0.f) ? span_ms / span_ticks : 1.0 / std::max(1, khz);
-    double t = 0.0;
-    for (int it = 0; it < m && e == hipSuccess; ++it) t += (double)(stamps[2 * it + 1] - stamps[2 * it]) * ms_per_tick;
+    double t[2] = {0.0, 0.0};
+    for (int it = 0; it < m && e == hipSuccess; ++it)
+        t[it & 1] += (double)(stamps[2 * it + 1] - stamps[2 * it]) * ms_per_tick;
     if (exec) (void)hipGraphExecDestroy(exec);
     (void)hipFree(d_ts);
     if (e != hipSuccess) return fail(ctx, POT3D_EDEVICE, std::string("kernel timing: ") + hipGetErrorString(e));
-    *ms_sweep = t / m;
+    *ms_even = t[0] / (m / 2);
+    *ms_odd = t[1] / (m / 2);
     return POT3D_OK;
 }
 
@@ -1375,7 +1403,7 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     fill_shape(ctx, *out);
     const bool fp32 = ctx->precision == POT3D_FP32_REFINED;
     const double per = ctx->precond == POT3D_PC_PHI_LINE ? (fp32 ? 40.0 : 80.0)
-                       : one_sweep(ctx) ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0);
+                       : one_sweep(ctx) ? sweep_bytes(fp32) : (fp32 ? 32.0 : 64.0);
     out->bytes_per_iter = per * (double)ctx->n;
     return POT3D_OK;
 }
@@ -1389,13 +1417,12 @@ int pot3d_time_kernels(pot3d_ctx *ctx, int reps, double *ms_update_p, double *ms
     int rc;
     if (one_sweep(ctx) && ctx->precision == POT3D_FP32_REFINED) {
         rc = time_sweeps<float>(ctx, ctx->r32, ctx->r32b, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps,
-                                ms_update_p);
-        *ms_update_r = 0.0;
+                                ms_update_p, ms_update_r);
     } else if (ctx->precision == POT3D_FP32_REFINED) {
         rc = time_pair<float>(ctx, ctx->r32, ctx->p32[0], ctx->p32[1], ctx->e32, ctx->sc32, reps, ms_update_p, ms_update_r);
     } else if (one_sweep(ctx)) {
-        rc = time_sweeps<double>(ctx, ctx->r, ctx->r2, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p);
-        *ms_update_r = 0.0;
+        rc = time_sweeps<double>(ctx, ctx->r, ctx->r2, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p,
+                                 ms_update_r);
     } else {
         rc = time_pair<double>(ctx, ctx->r, ctx->p[0], ctx->p[1], ctx->x, ctx->sc, reps, ms_update_p, ms_update_r);
     }

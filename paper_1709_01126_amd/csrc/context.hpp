@@ -135,6 +135,10 @@ void fill_tables(int nr, int nt, int np, const double *rf, const double *tf, con
 // workgroups, and the one-sweep kernel with `rows` box rows per wavefront.
 GridArgs make_grid(const pot3d_ctx *c, int tile, int target, int ci_fixed);
 GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target);
+// x update mode of sweep `it` of a captured sequence (SweepVecs::xmode), and
+// the HBM bytes per unknown per iteration of the one-sweep form that go with it.
+int sweep_xmode(int it);
+double sweep_bytes(bool fp32);
 // Allocate a context on `device` (tables, vectors, graphs).  serving = true:
 // no graph capture (the server's batched graph iterates it).
 int create_context(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,

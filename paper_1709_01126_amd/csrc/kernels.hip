@@ -805,6 +805,20 @@ stencil_wave_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 // iteration (read r, p_old, x; write r, p, x) against 64 for the two passes,
 // and one stencil launch and one finisher instead of two of each.
 //
+// x is needed only at the end, so sweeps can run in pairs that touch it once:
+// an even sweep j leaves x_{j-1} as it is, and the odd sweep j + 1 adds both
+// increments, alpha_{j-1} p_{j-1} + alpha_j p_j.  It has p_j (its p_old) and
+// r_j, hence z_j, and p_j = z_j + beta_j p_{j-1} gives
+// p_{j-1} = (p_j - z_j) / beta_j without reading it: 32 + 48 bytes per
+// unknown per pair of sweeps instead of 2 x 48, with r and p bitwise as
+// before.  z_j is recomputed bitwise (same r_j, same 1/diag), and the
+// rebuilt increment carries a rounding error of about
+// alpha_{j-1} |p_j| eps / beta_j, so the pairing is kept to
+// beta_j >= 1/64; otherwise (and for the restarts, beta = 0) the even sweep
+// updates x itself.  After the last sweep of a solve, x may still lack
+// alpha_{j-1} p_{j-1}; p_{j-1} is then intact in its buffer, and the first
+// workgroup of each sweep records which increment is owed (x_lag).
+//
 // p_j feeds A p_j on a one-cell ring around each cell, and A p_{j-1} is
 // needed on that ring too, so p_{j-1} is read with a two-cell ring.  A
 // workgroup owns tj x tk interior (theta, phi) cells over a chunk of radial
@@ -873,7 +887,14 @@ __device__ __forceinline__ GPtr<T> at_byte(GPtr<T> base, unsigned boff)
 #define SWEEP_AT(base, boff) at_byte((base), (boff))
 #endif
 
-template <int R, typename V>
+// Whether an even sweep running with alpha_{j-1}, beta_j leaves its x
+// increment to the odd sweep after it (which tests the same values).
+__device__ __forceinline__ bool defer_x(double alpha_prev, double beta)
+{
+    return alpha_prev == 0.0 || (beta >= 1.0 / 64.0 && isfinite(beta));
+}
+
+template <int R, typename V, int XM>
 __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V> &v, const RowCoef *__restrict__ rows,
                                            const V *__restrict__ rin, V *__restrict__ rout, const V *__restrict__ pold,
                                            V *__restrict__ pnew, V *__restrict__ xvec, const int b)
@@ -922,6 +943,19 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     const V ihk = (V)gih[CHK(kk, np)];
     const V ihs = ihm + ihk;   // the phi part of the diagonal, / pq
     const V alpha = (V)csc->alpha, beta = (V)csc->beta;
+    // x pairing: an even sweep that defers leaves x alone (xskip); the odd
+    // sweep after it adds xc (p_{j-1} - z_{j-1}) with xc = alpha_{j-2} / beta_{j-1}.
+    bool xskip = false;
+    V xc = V(0);
+    if (XM == 1) xskip = defer_x(csc->alpha, csc->beta);
+    if (XM == 2) {
+        const double ap = csc->alpha_prev, bp = csc->beta_prev;
+        if (ap != 0.0 && defer_x(ap, bp)) xc = (V)(ap / bp);
+    }
+    if (b == 0 && threadIdx.x == 0) {   // the increment x lacks if this is the last sweep
+        v.sc->x_lag = (XM == 1 && xskip) ? csc->alpha : 0.0;
+        v.sc->x_lag_p = (XM == 1 && xskip) ? (unsigned long long)pold : 0ull;
+    }
 
     // Per lane: the byte offset of the cell within a layer for each of this
     // wavefront's box rows (rows outside the grid read the nearest grid row),
@@ -955,7 +989,7 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
             rdst[m] = V(0);   // the box's outer ring needs no r
             if (e0 + m >= 1 && e0 + m < tjn + 3) rdst[m] = *SWEEP_AT(grin, lb + vrow[m]);
             xdst[m] = V(0);
-            if (own && oki[m] && col_in) xdst[m] = stream_load(SWEEP_AT(gx, lb + vrow[m]));
+            if (!xskip && own && oki[m] && col_in) xdst[m] = stream_load(SWEEP_AT(gx, lb + vrow[m]));
         }
     };
     // Row coefficients of the box rows of one layer, staged in LDS (three
@@ -1030,7 +1064,11 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
             if (own && oki[m] && col_in) {
                 stream_store(SWEEP_AT(grout, lb + vrow[m]), rn);
                 stream_store(SWEEP_AT(gpnew, lb + vrow[m]), qn);
-                stream_store(SWEEP_AT(gx, lb + vrow[m]), vfma<V>(alpha, pc, xo[m]));
+                if (!xskip) {
+                    V xn = xo[m];
+                    if (XM == 2) xn = vfma<V>(xc, pc - rv[m] * inv, xn);   // alpha_{j-2} p_{j-2}
+                    stream_store(SWEEP_AT(gx, lb + vrow[m]), vfma<V>(alpha, pc, xn));
+                }
                 acc0 = __builtin_fma((double)rn, (double)zn, acc0);
                 acc1 = __builtin_fma((double)rn, (double)rn, acc1);
             }
@@ -1109,17 +1147,17 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
 }
 #undef SWEEP_AT
 
-template <int R, typename V>
+template <int R, typename V, int XM>
 __global__ void __launch_bounds__(kThreads)
 stencil_sweep(GridArgs g, SweepVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ rin,
               V *__restrict__ rout, const V *__restrict__ pold, V *__restrict__ pnew, V *__restrict__ x)
 {
-    sweep_body<R, V>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
+    sweep_body<R, V, XM>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
 }
 
 // Batched sweeps: slot q owns workgroups [offset, offset + nblocks) of the
 // grid and runs exactly the arithmetic of its single-solve launch.
-template <int R, typename V>
+template <int R, typename V, int XM>
 __global__ void __launch_bounds__(kThreads)
 stencil_sweep_batch(const BatchSweep<V> *__restrict__ slots, int nslots)
 {
@@ -1127,7 +1165,7 @@ stencil_sweep_batch(const BatchSweep<V> *__restrict__ slots, int nslots)
     const int s = batch_slot(slots, nslots, bid);
     if (s < 0) return;
     const BatchSweep<V> sl = slots[s];
-    sweep_body<R, V>(sl.g, sl.v, sl.g.rows, sl.v.r_in, sl.v.r_out, sl.v.p_old, sl.v.p_new, sl.v.x, bid - sl.offset);
+    sweep_body<R, V, XM>(sl.g, sl.v, sl.g.rows, sl.v.r_in, sl.v.r_out, sl.v.p_old, sl.v.p_new, sl.v.x, bid - sl.offset);
 }
 
 // ---------------------------------------------------------------------------
@@ -1282,6 +1320,8 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
             } else {
                 const double alpha = rho / sigma;
                 const double rho_next = fma(alpha * alpha, s[4], fma(-2.0 * alpha, s[3], rho));
+                sc->alpha_prev = sc->alpha;
+                sc->beta_prev = sc->beta;
                 sc->alpha = alpha;
                 sc->beta = (rho_next > 0.0 && isfinite(rho_next)) ? rho_next / rho : 0.0;
             }
@@ -1644,6 +1684,24 @@ __global__ void resume_residual_kernel(const double *r64, float *r32, float *e32
         r32[q] = (float)(r64[q] * scale);
         e32[q] = 0.0f;
         pdst[q] = f * psrc[q];
+    }
+}
+
+// After the last sweep of a solve in which x is updated every other sweep:
+// x += x_lag p_{j-1}, if the last sweep left that increment (see the
+// one-sweep iteration).  Grid cells only (k < np).
+template <typename V>
+__global__ void x_catchup_kernel(V *x, const DevScalars *sc, long long nrows, int np, int pitch, long long npad)
+{
+    const double a = sc->x_lag;
+    if (a == 0.0) return;
+    const V *p = reinterpret_cast<const V *>(sc->x_lag_p);
+    const V av = (V)a;
+    const long long n = nrows * np;
+    for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (long long)gridDim.x * blockDim.x) {
+        const long long row = q / np;
+        const long long o = row * pitch + (q - row * np);
+        x[CHK(o, npad)] = vfma<V>(av, p[CHK(o, npad)], x[CHK(o, npad)]);
     }
 }
 
@@ -2032,14 +2090,23 @@ template hipError_t launch_stencil<double>(int, int, const GridArgs &, const Ste
 template hipError_t launch_stencil<float>(int, int, const GridArgs &, const StencilVecs<float> &, hipStream_t,
                                          hipEvent_t, hipEvent_t);
 
+template <int R, typename V>
+static void launch_sweep_x(const GridArgs &g, const SweepVecs<V> &v, hipStream_t s)
+{
+    const dim3 grid(g.nblocks), block(kThreads);
+    if (v.xmode == 1) stencil_sweep<R, V, 1><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x);
+    else if (v.xmode == 2) stencil_sweep<R, V, 2><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x);
+    else stencil_sweep<R, V, 0><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x);
+}
+
 template <typename V>
 hipError_t launch_sweep(int rows, const GridArgs &g, const SweepVecs<V> &v, hipStream_t s)
 {
-    const dim3 grid(g.nblocks), block(kThreads);
+    if (v.xmode < 0 || v.xmode > 2) return hipErrorInvalidValue;
     switch (rows) {
-    case 4: stencil_sweep<4, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
-    case 6: stencil_sweep<6, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
-    case 8: stencil_sweep<8, V><<<grid, block, 0, s>>>(g, v, g.rows, v.r_in, v.r_out, v.p_old, v.p_new, v.x); break;
+    case 4: launch_sweep_x<4, V>(g, v, s); break;
+    case 6: launch_sweep_x<6, V>(g, v, s); break;
+    case 8: launch_sweep_x<8, V>(g, v, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2050,9 +2117,9 @@ template hipError_t launch_sweep<float>(int, const GridArgs &, const SweepVecs<f
 template <typename V>
 int sweep_blocks_per_cu(int rows)
 {
-    const void *f = rows == 4   ? reinterpret_cast<const void *>(&stencil_sweep<4, V>)
-                    : rows == 6 ? reinterpret_cast<const void *>(&stencil_sweep<6, V>)
-                    : rows == 8 ? reinterpret_cast<const void *>(&stencil_sweep<8, V>)
+    const void *f = rows == 4   ? reinterpret_cast<const void *>(&stencil_sweep<4, V, 2>)
+                    : rows == 6 ? reinterpret_cast<const void *>(&stencil_sweep<6, V, 2>)
+                    : rows == 8 ? reinterpret_cast<const void *>(&stencil_sweep<8, V, 2>)
                                 : nullptr;
     int n = 0;
     if (!f || hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kThreads, 0) != hipSuccess) return 0;
@@ -2061,21 +2128,31 @@ int sweep_blocks_per_cu(int rows)
 template int sweep_blocks_per_cu<double>(int);
 template int sweep_blocks_per_cu<float>(int);
 
+template <int R, typename V>
+static void launch_sweep_batch_x(const BatchSweep<V> *slots, int nslots, int total_blocks, int xmode, hipStream_t s)
+{
+    const dim3 grid(total_blocks), block(kThreads);
+    if (xmode == 1) stencil_sweep_batch<R, V, 1><<<grid, block, 0, s>>>(slots, nslots);
+    else if (xmode == 2) stencil_sweep_batch<R, V, 2><<<grid, block, 0, s>>>(slots, nslots);
+    else stencil_sweep_batch<R, V, 0><<<grid, block, 0, s>>>(slots, nslots);
+}
+
 template <typename V>
-hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, hipStream_t s)
+hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, int xmode,
+                              hipStream_t s)
 {
     if (total_blocks <= 0) return hipSuccess;
-    const dim3 grid(total_blocks), block(kThreads);
+    if (xmode < 0 || xmode > 2) return hipErrorInvalidValue;
     switch (rows) {
-    case 4: stencil_sweep_batch<4, V><<<grid, block, 0, s>>>(slots, nslots); break;
-    case 6: stencil_sweep_batch<6, V><<<grid, block, 0, s>>>(slots, nslots); break;
-    case 8: stencil_sweep_batch<8, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case 4: launch_sweep_batch_x<4, V>(slots, nslots, total_blocks, xmode, s); break;
+    case 6: launch_sweep_batch_x<6, V>(slots, nslots, total_blocks, xmode, s); break;
+    case 8: launch_sweep_batch_x<8, V>(slots, nslots, total_blocks, xmode, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template hipError_t launch_sweep_batch<double>(int, const BatchSweep<double> *, int, int, hipStream_t);
-template hipError_t launch_sweep_batch<float>(int, const BatchSweep<float> *, int, int, hipStream_t);
+template hipError_t launch_sweep_batch<double>(int, const BatchSweep<double> *, int, int, int, hipStream_t);
+template hipError_t launch_sweep_batch<float>(int, const BatchSweep<float> *, int, int, int, hipStream_t);
 
 template <int TJ, typename V>
 hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, dim3 grid, hipStream_t s)
@@ -2237,6 +2314,16 @@ hipError_t launch_resume_residual(const double *r64, float *r32, float *e32, con
     resume_residual_kernel<<<stream_blocks(npad), 256, 0, s>>>(r64, r32, e32, psrc, pdst, npad, sc, f);
     return hipGetLastError();
 }
+
+template <typename V>
+hipError_t launch_x_catchup(V *x, const DevScalars *sc, int nr, int nt, int np, int pitch, hipStream_t s)
+{
+    const long long nrows = (long long)nr * nt, npad = nrows * pitch;
+    x_catchup_kernel<V><<<stream_blocks(nrows * np), 256, 0, s>>>(x, sc, nrows, np, pitch, npad);
+    return hipGetLastError();
+}
+template hipError_t launch_x_catchup<double>(double *, const DevScalars *, int, int, int, int, hipStream_t);
+template hipError_t launch_x_catchup<float>(float *, const DevScalars *, int, int, int, int, hipStream_t);
 
 hipError_t launch_add_correction(double *x64, const float *e32, long long npad, const DevScalars *sc, hipStream_t s)
 {

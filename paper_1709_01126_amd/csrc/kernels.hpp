@@ -48,7 +48,8 @@ template <typename V>
 int sweep_blocks_per_cu(int rows);
 // Batched sweeps over a device slot table (every active slot runs `rows`).
 template <typename V>
-hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, hipStream_t s);
+hipError_t launch_sweep_batch(int rows, const BatchSweep<V> *slots, int nslots, int total_blocks, int xmode,
+                              hipStream_t s);
 inline bool valid_sweep_rows(int rows) { return rows == 4 || rows == 6 || rows == 8; }
 
 // Checked builds: the source line of the first out-of-range index seen since
@@ -111,6 +112,10 @@ hipError_t launch_resume_residual(const double *r64, float *r32, float *e32, con
                                   long long npad, const DevScalars *sc, float f, hipStream_t s);
 // x64 += double(e32) / sc->scale (all npad elements)
 hipError_t launch_add_correction(double *x64, const float *e32, long long npad, const DevScalars *sc, hipStream_t s);
+// x += x_lag p_lag (both from sc) on the grid cells, if the last sweep left x
+// one increment behind (sweeps with xmode 1 and 2); nothing otherwise.
+template <typename V>
+hipError_t launch_x_catchup(V *x, const DevScalars *sc, int nr, int nt, int np, int pitch, hipStream_t s);
 // per-workgroup partials of r.z and r.r (z = D^-1 r) for an FP32 vector; nblocks <= cap
 hipError_t launch_dots_rz(const GridArgs &g, const float *r, double *partial, int nblocks, hipStream_t s);
 

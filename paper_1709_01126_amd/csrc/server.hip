@@ -182,7 +182,7 @@ int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *con
     if (sv->sweep) {
         // 2m sweeps: the parity of the r and p buffers continues across replays
         for (int it = 0; it < 2 * sv->graph_m && e == hipSuccess; ++it) {
-            e = launch_sweep_batch<V>(sv->sweep_rows, ds[it & 1], sv->max_slots, wp, s);
+            e = launch_sweep_batch<V>(sv->sweep_rows, ds[it & 1], sv->max_slots, wp, sweep_xmode(it), s);
             if (e == hipSuccess) e = launch_finish_batch(kFinSweep, sv->d_finp, sv->max_slots, s);
         }
     }
@@ -444,7 +444,10 @@ int retire(pot3d_server *sv, Slot &sl, DevScalars fin, int total_iters, int oute
     double rel = 0.0;
     SV_TRY(sv, hipEventRecord(c->ev_loop1, sv->stream));
     const bool fp32 = sv->precision == POT3D_FP32_REFINED;
-    const double per_unknown = sv->sweep ? (fp32 ? 24.0 : 48.0) : (fp32 ? 32.0 : 64.0);
+    const double per_unknown = sv->sweep ? sweep_bytes(fp32) : (fp32 ? 32.0 : 64.0);
+    // the x increment the slot's last sweep may have left (FP64; refined
+    // slots caught up their correction before the outer test)
+    if (sv->sweep && !fp32) SV_TRY(sv, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, sv->stream));
     const int rc = finish_solve(c, dst, hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
                                 per_unknown, &iters, &rel);
     if (rc != POT3D_OK && rc != POT3D_ENOCONV && rc != POT3D_EBREAKDOWN) return sfail(sv, rc, pot3d_last_error(c));
@@ -677,6 +680,9 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
                 if (rc != POT3D_OK) return rc;
                 continue;
             }
+            if (sv->sweep)
+                SV_TRY(sv, launch_x_catchup<float>(sl.ctx->e32, sl.ctx->sc32, sl.ctx->nr, sl.ctx->nt, sl.ctx->np,
+                                                   sl.ctx->pitch, s));
             SV_CALL(sv, sl.ctx, refined_correct(sl.ctx, s));
             const int rc = refined_advance(sv, sl);
             if (rc != POT3D_OK) return rc;

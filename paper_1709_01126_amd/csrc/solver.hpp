@@ -47,6 +47,11 @@ struct alignas(64) DevScalars {
     int sweep;         // one-sweep iteration: sweeps done since the start
     int pad[2];
     double scale;      // refinement: 1 / ||r64|| used to normalise the FP32 residual
+    // One-sweep iteration with x updated every other sweep (SweepVecs::xmode):
+    double alpha_prev; // alpha and beta that the previous sweep ran with
+    double beta_prev;
+    double x_lag;      // alpha of the increment x still lacks after the last sweep (0: none) ...
+    unsigned long long x_lag_p;   // ... and the search direction it multiplies (device address)
 };
 
 // Launch geometry and tables common to every stencil launch.
@@ -100,10 +105,13 @@ struct SweepVecs {
     const V *p_old;   // p_{j-1}
     V *p_new;         // p_j
     V *x;             // x_{j-1} in, x_j out
-    const DevScalars *sc;   // alpha_{j-1}, beta_j
+    DevScalars *sc;   // alpha_{j-1}, beta_j (read); x_lag, x_lag_p (written by the first workgroup)
     double *partial;  // [5][nblocks]: r.z, r.r, p.Ap, z.Ap, Ap.D^-1 Ap
     int ignore_done;  // 1: run even when sc->done is set
     unsigned long long *tstamp;   // timing runs only, as in StencilVecs
+    int xmode;        // 0: x_j = x_{j-1} + alpha p_{j-1} in every sweep.  Sweeps in pairs:
+                      // 1 (even sweeps): x is left for the next sweep; 2 (odd sweeps): x
+                      // takes both increments, p_{j-2} rebuilt as (p_{j-1} - z_{j-1}) / beta_{j-1}
 };
 
 // One slot of a batched stencil launch (device-resident table).  `out` is the

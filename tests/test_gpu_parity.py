@@ -154,7 +154,8 @@ def test_solve_matches_oracle(case, iteration):
     print(f"[solve] {label(case)} iteration={iteration} iters gpu={it} oracle={ref['iters']} "
           f"true_relres={rr:.2e}", flush=True)
     assert stats["iteration"] == iteration
-    assert stats["bytes_per_iter"] == (48.0 if iteration == P.ITER_ONE_SWEEP else 64.0) * stats["n"]
+    # one sweep: r and p read and written every sweep, x every other sweep
+    assert stats["bytes_per_iter"] == (40.0 if iteration == P.ITER_ONE_SWEEP else 64.0) * stats["n"]
     assert st == P.OK and ref["status"] == oracle.OK
     assert iters_close(it, ref["iters"]), (it, ref["iters"])
     check_solution(phi, ref["phi"])
@@ -178,6 +179,29 @@ def test_fixed_iteration_count_parity(case, iteration):
             phi, st, it, _ = gpu_solve(s, br, 0.0, K)
         assert st == P.ENOCONV and so == oracle.ENOCONV and it == io == K
         check_solution(phi, xo, tol=1e-11)
+
+
+@pytest.mark.parametrize("case", [GRIDS[4], GRIDS[6]], ids=label)
+def test_x_every_other_sweep_matches_every_sweep(case, monkeypatch):
+    """x updated once per pair of sweeps (the default) against every sweep:
+    the same r and p, so the same iteration counts; x differs by rounding only.
+    Solves that end after an even sweep (x one increment behind, caught up
+    after the loop) and after an odd one, and a converged solve."""
+    rf, tf, pf = make_faces(*case)
+    br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
+    runs = [(0.0, 2), (0.0, 17), (0.0, 50), (0.0, 51), (1e-10, 100_000)]
+    got = {}
+    for mode in ("2", "1"):
+        monkeypatch.setenv("POT3D_SWEEP_X", mode)
+        with P.Solver(rf, tf, pf) as s:
+            got[mode] = [gpu_solve(s, br, tol, K) for tol, K in runs]
+            assert s.stats()["bytes_per_iter"] == (40.0 if mode == "2" else 48.0) * s.stats()["n"]
+    for (tol, K), a, b in zip(runs, got["2"], got["1"]):
+        assert a[1] == b[1] and a[2] == b[2], (K, a[1:3], b[1:3])
+        scale = np.abs(b[0]).max()
+        assert np.abs(a[0] - b[0]).max() <= 1e-13 * scale, (K, np.abs(a[0] - b[0]).max() / scale)
+        print(f"[x pairing] {label(case)} K={K} iters={a[2]} max diff/max|Phi| = "
+              f"{np.abs(a[0] - b[0]).max() / scale:.1e}", flush=True)
 
 
 def test_small_workload_parity_and_poles():
@@ -250,7 +274,8 @@ def test_edge_cases(iteration):
                                  {"POT3D_SWEEP_ROWS": "6"}, {"POT3D_SWEEP_ROWS": "8"},
                                  {"POT3D_SWEEP_TK": "1"}, {"POT3D_SWEEP_TK": "16"}, {"POT3D_SWEEP_TK": "60"},
                                  {"POT3D_SWEEP_CI": "1"}, {"POT3D_SWEEP_CI": "1000"},
-                                 {"POT3D_REVERSE_S": "1", "POT3D_TARGET_BLOCKS_S": "7"}])
+                                 {"POT3D_REVERSE_S": "1", "POT3D_TARGET_BLOCKS_S": "7"},
+                                 {"POT3D_SWEEP_X": "1"}])
 def test_launch_shapes_agree(env, monkeypatch):
     for k, v in env.items():
         monkeypatch.setenv(k, v)
