@@ -894,16 +894,33 @@ __device__ __forceinline__ bool defer_x(double alpha_prev, double beta)
     return alpha_prev == 0.0 || (beta >= 1.0 / 64.0 && isfinite(beta));
 }
 
+// LDS of the sweep, one object per (R, V): kernels that inline the body
+// twice (the two x modes of an even sweep) share it.
+template <int R, typename V>
+struct alignas(16) SweepLds {   // 16: the coefficient rows are read 16 bytes at a time
+    alignas(16) V lp[3][kWaves * R][kWave];     // p_{j-1} of three layers
+    alignas(16) V lq[3][kWaves * R][kWave];     // p_j of three layers
+    alignas(16) double lc[3][kWaves * R][8];    // row coefficients of three layers
+    double red[kWaves][5];
+};
+template <int R, typename V>
+__device__ __forceinline__ SweepLds<R, V> &sweep_lds()
+{
+    __shared__ SweepLds<R, V> lds;
+    return lds;
+}
+
 template <int R, typename V, int XM>
 __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V> &v, const RowCoef *__restrict__ rows,
                                            const V *__restrict__ rin, V *__restrict__ rout, const V *__restrict__ pold,
                                            V *__restrict__ pnew, V *__restrict__ xvec, const int b)
 {
     constexpr int ER = kWaves * R;
-    __shared__ V lp[3][ER][kWave];   // p_{j-1} of three layers
-    __shared__ V lq[3][ER][kWave];   // p_j of three layers
-    __shared__ double lc[3][ER][8];  // row coefficients of three layers
-    __shared__ double red[kWaves][5];
+    SweepLds<R, V> &lds = sweep_lds<R, V>();
+    auto &lp = lds.lp;
+    auto &lq = lds.lq;
+    auto &lc = lds.lc;
+    auto &red = lds.red;
     static_assert(ER * 8 <= kThreads, "coefficient staging");
 
     const CPtr<const DevScalars> csc = to_const(v.sc);
@@ -943,18 +960,18 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     const V ihk = (V)gih[CHK(kk, np)];
     const V ihs = ihm + ihk;   // the phi part of the diagonal, / pq
     const V alpha = (V)csc->alpha, beta = (V)csc->beta;
-    // x pairing: an even sweep that defers leaves x alone (xskip); the odd
-    // sweep after it adds xc (p_{j-1} - z_{j-1}) with xc = alpha_{j-2} / beta_{j-1}.
-    bool xskip = false;
+    // x pairing: an even sweep leaves x alone (xskip; the kernel has chosen
+    // this body only if defer_x holds); the odd sweep after it adds
+    // xc (p_{j-1} - z_{j-1}) with xc = alpha_{j-2} / beta_{j-1}.
+    constexpr bool xskip = XM == 1;
     V xc = V(0);
-    if (XM == 1) xskip = defer_x(csc->alpha, csc->beta);
     if (XM == 2) {
         const double ap = csc->alpha_prev, bp = csc->beta_prev;
         if (ap != 0.0 && defer_x(ap, bp)) xc = (V)(ap / bp);
     }
     if (b == 0 && threadIdx.x == 0) {   // the increment x lacks if this is the last sweep
-        v.sc->x_lag = (XM == 1 && xskip) ? csc->alpha : 0.0;
-        v.sc->x_lag_p = (XM == 1 && xskip) ? (unsigned long long)pold : 0ull;
+        v.sc->x_lag = xskip ? csc->alpha : 0.0;
+        v.sc->x_lag_p = xskip ? (unsigned long long)pold : 0ull;
     }
 
     // Per lane: the byte offset of the cell within a layer for each of this
@@ -1147,11 +1164,23 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
 }
 #undef SWEEP_AT
 
+// An even sweep (XM = 1) whose alpha_{j-1}, beta_j do not allow the
+// deferral runs the body that updates x itself.  The choice is made once, at
+// the top, between two inlined bodies, so that each keeps exact memory-wait
+// counts (loads under a run-time condition would make the compiler's waits
+// conservative).
 template <int R, typename V, int XM>
 __global__ void __launch_bounds__(kThreads)
 stencil_sweep(GridArgs g, SweepVecs<V> v, const RowCoef *__restrict__ rows, const V *__restrict__ rin,
               V *__restrict__ rout, const V *__restrict__ pold, V *__restrict__ pnew, V *__restrict__ x)
 {
+    if (XM == 1) {
+        const CPtr<const DevScalars> csc = to_const(v.sc);
+        if (!defer_x(csc->alpha, csc->beta)) {
+            sweep_body<R, V, 0>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
+            return;
+        }
+    }
     sweep_body<R, V, XM>(g, v, rows, rin, rout, pold, pnew, x, blockIdx.x);
 }
 
@@ -1165,6 +1194,14 @@ stencil_sweep_batch(const BatchSweep<V> *__restrict__ slots, int nslots)
     const int s = batch_slot(slots, nslots, bid);
     if (s < 0) return;
     const BatchSweep<V> sl = slots[s];
+    if (XM == 1) {   // as in stencil_sweep
+        const CPtr<const DevScalars> csc = to_const(sl.v.sc);
+        if (!defer_x(csc->alpha, csc->beta)) {
+            sweep_body<R, V, 0>(sl.g, sl.v, sl.g.rows, sl.v.r_in, sl.v.r_out, sl.v.p_old, sl.v.p_new, sl.v.x,
+                                bid - sl.offset);
+            return;
+        }
+    }
     sweep_body<R, V, XM>(sl.g, sl.v, sl.g.rows, sl.v.r_in, sl.v.r_out, sl.v.p_old, sl.v.p_new, sl.v.x, bid - sl.offset);
 }
 
