@@ -550,6 +550,7 @@ def main():
         with Solver(*faces, precision=FP32_REFINED, device=0) as s32:
             s32.solve_device(d_br, d_phi, 0.0, 8)
             ms_s32e, ms_s32o = s32.time_kernels(args.kernel_reps)
+            fp32_form = "one-sweep" if s32.stats()["iteration"] == pot3d.ITER_ONE_SWEEP else "two-pass"
         # counter calibration: a device copy of N doubles whose source is not in
         # the 256 MB memory-side cache (a 1 GB fill runs in between)
         src = torch.ones(w.n, dtype=torch.float64, device=dev)
@@ -561,7 +562,9 @@ def main():
         del flush
         print(json.dumps({"profile_kernels": w.describe(), "sweep_even_ms": ms_se, "sweep_odd_ms": ms_so,
                           "update_p_ms": ms_p, "update_r_ms": ms_r,
-                          "sweep_fp32_even_ms": ms_s32e, "sweep_fp32_odd_ms": ms_s32o,
+                          "fp32_inner": {"form": fp32_form, "ms": [ms_s32e, ms_s32o],
+                                         "kernels": "even, odd sweep" if fp32_form == "one-sweep" else
+                                                    "p update, r/x update"},
                           "copy_bytes_each_way": 8 * w.n, "launch": solver.stats()}), flush=True)
         solver.close()
         return
@@ -856,6 +859,7 @@ def large_grid_leg(torch, dev, name):
            "iters_per_s": round(1e6 / loop_us, 2),
            "gbs_alg_per_iteration": round(stats["bytes_per_iter"] / (loop_us * 1e-6) / 1e9, 1),
            "sweep_ms_even_odd": [round(ms_e, 4), round(ms_o, 4)], "sweep_ms_mean": round(ms_sweep, 4),
+           "sweep_traffic_even_odd": [load_traffic(w.name, "sweep_even"), load_traffic(w.name, "sweep_odd")],
            "sweep_gbs_alg": round(stats["bytes_per_iter"] / (ms_sweep * 1e-3) / 1e9, 1),
            "sweep_frac": round(stats["bytes_per_iter"] / (ms_sweep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
            "launch": {k2: stats[k2] for k2 in ("sweep_rows", "chunk_s", "blocks_s", "pitch")}}
