@@ -834,7 +834,10 @@ stencil_wave_batch(const BatchSlot<V> *__restrict__ slots, int nslots)
 //     layers a-2, a-1 from LDS planes, of layer a from registers).
 // Each vector has three LDS layer slots in rotation: one barrier per layer.
 // The row coefficients of three layers are staged in LDS too, and r, x and
-// p_{j-1} of the next layers are loaded one layer ahead.
+// p_{j-1} of the next layers are loaded one layer ahead.  The coefficients
+// are loaded a step before they are written to LDS: a vector-memory wait
+// covers every load issued before it, so writing them in the step that loads
+// them would wait for that step's other loads too.
 // ---------------------------------------------------------------------------
 // Reciprocal of a positive normal value: the hardware estimate refined by
 // two Newton steps y <- y + y (1 - d y), each of which squares the relative
@@ -847,7 +850,14 @@ __device__ __forceinline__ double recip(double d)
     e = __builtin_fma(-d, y, 1.0);
     return __builtin_fma(y, e, y);
 }
-__device__ __forceinline__ float recip(float d) { return 1.0f / d; }
+// FP32: the estimate and one Newton step (about an ulp; the IEEE division
+// is three times the instructions).  Both sweeps of a pair use it, so the
+// odd sweep recomputes the even sweep's z bitwise.
+__device__ __forceinline__ float recip(float d)
+{
+    const float y = __builtin_amdgcn_rcpf(d);
+    return __builtin_fmaf(y, __builtin_fmaf(-d, y, 1.0f), y);
+}
 
 // Lane l receives lane l-1 (shr) or l+1 (shl); the lane past the wavefront's
 // end receives 0 (DPP bound control: no initialised destination needed).
@@ -1011,15 +1021,22 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     };
     // Row coefficients of the box rows of one layer, staged in LDS (three
     // layers in rotation) and read back as broadcasts: rm rp tm tp s pq.
-    auto stage_coef = [&](int a) {
+    // load_coef returns this thread's value; put_coef writes it a step later.
+    auto load_coef = [&](int a) -> double {
         const int t = threadIdx.x;
+        double v = 0.0;
         if (t < ER * 8) {
             const int e = t >> 3, f = t & 7;
             const int jc = min(max(j0 - 2 + e, 0), nt - 1);
             const int ac = min(max(a, 0), nr - 1);
             const GPtr<const double> src = to_global(reinterpret_cast<const double *>(rows));
-            lc[slot(a)][e][f] = src[CHK(((long long)ac * nt + jc) * 8 + f, 8LL * nr * nt)];
+            v = src[CHK(((long long)ac * nt + jc) * 8 + f, 8LL * nr * nt)];
         }
+        return v;
+    };
+    auto put_coef = [&](int a, double v) {
+        const int t = threadIdx.x;
+        if (t < ER * 8) lc[slot(a)][t >> 3][t & 7] = v;
     };
     auto coef = [&](int sl, int e) -> RowCoef {
         RowCoef r;
@@ -1052,16 +1069,17 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     // to rv_n, xo_n).  z1, i1: z_j and 1/diag of layer a - 1 (stage B); this
     // step's go to za, ia.  Each wavefront reads its own rows of the LDS
     // planes at any time (it alone writes them) and other rows only across a
-    // barrier.
+    // barrier.  cq: this thread's coefficient of layer a + 1 (loaded in the
+    // step before, written to LDS at this step's end); cq_n receives layer a + 2's.
     auto step = [&](int a, V (&rv)[R], V (&xo)[R], V (&rv_n)[R], V (&xo_n)[R], V (&z1)[R], V (&i1_)[R], V (&za)[R],
-                    V (&ia)[R]) {
+                    V (&ia)[R], double cq, double &cq_n) {
         const bool own = a >= i0 && a < i1;
         const unsigned lb = layer_b(a);
         const int sa = slot(a), sa1 = slot(a + 1), sb = slot(a - 1), sb2 = slot(a - 2);
         V pn[R];
         load_p(a + 2, pn);
         load_rx(a + 1, rv_n, xo_n);
-        stage_coef(a + 1);
+        cq_n = load_coef(a + 2);
         V qa[R];
 #pragma unroll
         for (int m = 0; m < R; ++m) {
@@ -1107,11 +1125,13 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
         }
 #pragma unroll
         for (int m = 0; m < R; ++m) lp[slot(a + 2)][e0 + m][lane] = pn[m];
+        put_coef(a + 1, cq);   // slot(a + 1) held layer a - 2, which no stage reads in this step
         __syncthreads();
     };
 
     V rvA[R], xoA[R], rvB[R], xoB[R], zA[R], iA[R], zB[R], iB[R];
-    stage_coef(i0 - 1);
+    put_coef(i0 - 1, load_coef(i0 - 1));
+    double cA = load_coef(i0), cB = 0.0;
     load_rx(i0 - 1, rvA, xoA);
     {
         V t0[R], t1[R], t2[R];
@@ -1129,10 +1149,10 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     __syncthreads();
     int a = i0 - 1;
     for (; a + 1 <= i1; a += 2) {
-        step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB);
-        step(a + 1, rvB, xoB, rvA, xoA, zB, iB, zA, iA);
+        step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB, cA, cB);
+        step(a + 1, rvB, xoB, rvA, xoA, zB, iB, zA, iA, cB, cA);
     }
-    if (a <= i1) step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB);
+    if (a <= i1) step(a, rvA, xoA, rvB, xoB, zA, iA, zB, iB, cA, cB);
 
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {

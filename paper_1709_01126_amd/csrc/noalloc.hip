@@ -224,6 +224,7 @@ extern "C" int pot3d_solve_noalloc(const double *r_faces, int nr, const double *
             sv.x = x;
             sv.sc = sc;
             sv.partial = partial;
+            sv.xmode = sweep_xmode((int)(j & 1));   // x once per pair of sweeps; j starts even
             NA_TRY(launch_sweep<double>(4, gs, sv, s));
             NA_TRY(launch_finish(kFinSweep, sc, partial, gs.nblocks, s));
         }
@@ -233,6 +234,8 @@ extern "C" int pot3d_solve_noalloc(const double *r_faces, int nr, const double *
     }
     if (!h_sc.done) return fail(nullptr, POT3D_EDEVICE, "iteration loop ended without the device done flag");
     const DevScalars fin = h_sc;
+    // the x increment the last sweep may have left to a next one
+    NA_TRY(launch_x_catchup<double>(x, sc, nr, nt, np, shape.pitch, s));
 
     // the answer: gauge (closed wall), true residual, Phi into the caller's array
     if (fin.zero_solution) NA_TRY(launch_fill<double>(x, shape.npad, 0.0, s));
