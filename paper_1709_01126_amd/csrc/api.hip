@@ -1466,6 +1466,8 @@ int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc)
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
     const long long rows = (long long)ctx->nr * ctx->nt;
     ctx->line_blocks = (int)std::max<long long>(1, std::min<long long>((rows + kWaves - 1) / kWaves, ctx->max_blocks));
+    if (const int lb = env_int("POT3D_LINE_BLOCKS", 0); lb > 0)   // launch-width experiments
+        ctx->line_blocks = std::min(lb, ctx->line_blocks);
     if (ctx->precision == POT3D_FP64) {
         if (!ctx->z) {
             HIP_TRY(ctx, dalloc(&ctx->z, (size_t)ctx->npad));
