@@ -1465,7 +1465,13 @@ int pot3d_set_preconditioner(pot3d_ctx *ctx, int pc)
     DeviceGuard guard(ctx->device);
     if (!guard.ok) return fail(ctx, POT3D_EDEVICE, "hipSetDevice failed");
     const long long rows = (long long)ctx->nr * ctx->nt;
-    ctx->line_blocks = (int)std::max<long long>(1, std::min<long long>((rows + kWaves - 1) / kWaves, ctx->max_blocks));
+    // one wave of resident workgroups, each wavefront walking rows with the
+    // grid's stride (wider grids measured slower at 151 x 301 x 601)
+    const int per_cu = ctx->precision == POT3D_FP64 ? line_blocks_per_cu<double>(ctx->np)
+                                                    : line_blocks_per_cu<float>(ctx->np);
+    ctx->line_blocks = (int)std::max<long long>(
+        1, std::min<long long>({(rows + kWaves - 1) / kWaves, (long long)ctx->max_blocks,
+                                (long long)std::max(1, per_cu) * ctx->num_cu}));
     if (const int lb = env_int("POT3D_LINE_BLOCKS", 0); lb > 0)   // launch-width experiments
         ctx->line_blocks = std::min(lb, ctx->line_blocks);
     if (ctx->precision == POT3D_FP64) {

@@ -1475,15 +1475,20 @@ finish_batch(int which, const BatchFin *__restrict__ fins, int nslots)
 // With d / (2 w) = 1 + e, mu = 1 / (1 + e + sqrt(e (2 + e))), free of
 // cancellation for small e (pole rows) and large e alike.
 //
-// One wavefront solves one row, cell k = 64 q + lane in block q.  Each
-// recurrence runs over the blocks in order: an inclusive scan across the 64
-// lanes (lane shuffles with multipliers mu^1, mu^2, mu^4, ..), plus the carry
-// from the neighbouring block times the power of mu that it travels.  The
+// One wavefront solves one row.  Lane l owns the run of cells
+// [l NB, l NB + n_l), n_l = min(NB, max(0, np - l NB)): the row moves through
+// LDS from the coalesced layout (cell 64 q + lane) to these runs and back.
+// Each recurrence runs within a lane's run from a zero start, then an
+// inclusive scan across the 64 lanes joins the runs: a run is the affine map
+// c -> mu^n_l c + E_l (E_l its end value from a zero start), and maps compose
+// as (M1, E1) then (M2, E2) = (M1 M2, E1 M2 + E2).  The carry into run l then
+// enters its cell t with mu^(t + 1) (forward; mu^(n_l - t) backward).  The
 // periodic wrap is closed afterwards: the value that comes round the row is
 // the non-periodic end value divided by 1 - mu^np, and it enters every cell
-// with its own power of mu.  Every value is FP64; each row reads r once and
-// writes z once (16 bytes per unknown), keeping a copy of r in LDS for r.z.
-// Per-workgroup partial sums of r.z and r.r follow in fixed order.
+// with its own power of mu (the scan's products give mu^(l NB) and
+// mu^(np - (l + 1) NB)).  Every value is FP64; each row reads r once and
+// writes z once (16 bytes per unknown in FP64 storage).  Per-workgroup
+// partial sums of r.z and r.r follow in fixed order.
 // ---------------------------------------------------------------------------
 // m^e for an integer e >= 0 by binary powering.
 __device__ __forceinline__ double powi(double m, int e)
@@ -1495,6 +1500,15 @@ __device__ __forceinline__ double powi(double m, int e)
         e >>= 1;
     }
     return r;
+}
+
+// Orders one wavefront's LDS accesses across lanes (a row moving between
+// layouts): release and acquire fences at wavefront scope around a wave barrier.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // A double moved across lanes by a DPP row shift (row_shr:n is 0x110 + n,
@@ -1515,54 +1529,73 @@ __device__ __forceinline__ double lane_value(double v, int l)
                             __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
-// One block of 64 cells of a first-order recurrence, carried in from the
-// previous block.  Forward (UP): s_l = x_l + mu s_{l-1}, with s_{-1} = carry.
-// Backward: s_l = x_l + mu s_{l+1}, with s_64 = carry.  First an inclusive
-// scan inside each 16-lane row (DPP shifts by 1, 2, 4, 8 with multipliers
-// mu, mu^2, mu^4, mu^8), then the rows are chained through their end values
-// (uniform), and each lane adds its row's entry value times mu^(distance).
-// Returns s_l; *carry becomes the value at the far end of the block.
+// Inclusive scans of affine maps c -> M c + E across the 64 lanes, without
+// LDS: DPP shifts by 1, 2, 4, 8 inside each 16-lane row, then the rows are
+// chained through their composites read out of one lane each.  UP: lane l
+// ends with the composite of lanes 0..l applied in order, (M1, E1) then
+// (M2, E2) = (M1 M2, E1 M2 + E2).  Down: the composite of lanes l..63 with
+// the lanes to the right applied first, (M, F) of l then the rest R =
+// (M Mr, F + M Fr).
 template <bool UP>
-__device__ __forceinline__ double block_recurrence(double x, double &carry, const double (&mpow)[5], double pw_row,
-                                                   int row)
+__device__ __forceinline__ void affine_scan(double &M, double &E, int lane)
 {
-    double sv = x;
+    // Branch-free: a DPP read of a lane that is switched off returns 0, so the
+    // shifts must run with every lane on.  A source outside the row reads
+    // (0, 0), which the step turns into the identity (1, 0) by adding 1 to M.
+    const int rl = lane & 15, row = lane >> 4;
+    auto step = [&](double Mo, double Eo, bool ok) {
+        E = __builtin_fma(Eo, M, E);
+        M = (Mo + (ok ? 0.0 : 1.0)) * M;
+    };
     if (UP) {
-        sv = __builtin_fma(mpow[0], row_shift<0x111>(sv), sv);
-        sv = __builtin_fma(mpow[1], row_shift<0x112>(sv), sv);
-        sv = __builtin_fma(mpow[2], row_shift<0x114>(sv), sv);
-        sv = __builtin_fma(mpow[3], row_shift<0x118>(sv), sv);
-        // row r ends at lane 16 r + 15; P_r is the value just before row r
-        const double e0 = lane_value(sv, 15), e1 = lane_value(sv, 31), e2 = lane_value(sv, 47),
-                     e3 = lane_value(sv, 63);
-        const double p0 = carry;
-        const double p1 = __builtin_fma(mpow[4], p0, e0);
-        const double p2 = __builtin_fma(mpow[4], p1, e1);
-        const double p3 = __builtin_fma(mpow[4], p2, e2);
-        carry = __builtin_fma(mpow[4], p3, e3);
-        const double pin = row == 0 ? p0 : row == 1 ? p1 : row == 2 ? p2 : p3;
-        return __builtin_fma(pw_row, pin, sv);   // pw_row = mu^(lane % 16 + 1)
+        { const double Mo = row_shift<0x111>(M), Eo = row_shift<0x111>(E); step(Mo, Eo, rl >= 1); }
+        { const double Mo = row_shift<0x112>(M), Eo = row_shift<0x112>(E); step(Mo, Eo, rl >= 2); }
+        { const double Mo = row_shift<0x114>(M), Eo = row_shift<0x114>(E); step(Mo, Eo, rl >= 4); }
+        { const double Mo = row_shift<0x118>(M), Eo = row_shift<0x118>(E); step(Mo, Eo, rl >= 8); }
+        // rows: prefix composites of rows 0, 0-1, 0-2 from lanes 15, 31, 47
+        const double m0 = lane_value(M, 15), e0 = lane_value(E, 15);
+        const double m1 = lane_value(M, 31), e1 = lane_value(E, 31);
+        const double m2 = lane_value(M, 47), e2 = lane_value(E, 47);
+        const double p1m = m0 * m1, p1e = __builtin_fma(e0, m1, e1);     // rows 0-1
+        const double p2m = p1m * m2, p2e = __builtin_fma(p1e, m2, e2);   // rows 0-2
+        const double pm = row == 0 ? 1.0 : row == 1 ? m0 : row == 2 ? p1m : p2m;
+        const double pe = row == 0 ? 0.0 : row == 1 ? e0 : row == 2 ? p1e : p2e;
+        E = __builtin_fma(pe, M, E);
+        M = pm * M;
     } else {
-        sv = __builtin_fma(mpow[0], row_shift<0x101>(sv), sv);
-        sv = __builtin_fma(mpow[1], row_shift<0x102>(sv), sv);
-        sv = __builtin_fma(mpow[2], row_shift<0x104>(sv), sv);
-        sv = __builtin_fma(mpow[3], row_shift<0x108>(sv), sv);
-        // row r starts at lane 16 r; Q_r is the value just after row r
-        const double b0 = lane_value(sv, 0), b1 = lane_value(sv, 16), b2 = lane_value(sv, 32),
-                     b3 = lane_value(sv, 48);
-        const double q3 = carry;
-        const double q2 = __builtin_fma(mpow[4], q3, b3);
-        const double q1 = __builtin_fma(mpow[4], q2, b2);
-        const double q0 = __builtin_fma(mpow[4], q1, b1);
-        carry = __builtin_fma(mpow[4], q0, b0);
-        const double qin = row == 0 ? q0 : row == 1 ? q1 : row == 2 ? q2 : q3;
-        return __builtin_fma(pw_row, qin, sv);   // pw_row = mu^(16 - lane % 16)
+        { const double Mo = row_shift<0x101>(M), Eo = row_shift<0x101>(E); step(Mo, Eo, rl + 1 < 16); }
+        { const double Mo = row_shift<0x102>(M), Eo = row_shift<0x102>(E); step(Mo, Eo, rl + 2 < 16); }
+        { const double Mo = row_shift<0x104>(M), Eo = row_shift<0x104>(E); step(Mo, Eo, rl + 4 < 16); }
+        { const double Mo = row_shift<0x108>(M), Eo = row_shift<0x108>(E); step(Mo, Eo, rl + 8 < 16); }
+        // rows: suffix composites of rows 3, 2-3, 1-3 from lanes 48, 32, 16
+        const double m3 = lane_value(M, 48), e3 = lane_value(E, 48);
+        const double m2 = lane_value(M, 32), e2 = lane_value(E, 32);
+        const double m1 = lane_value(M, 16), e1 = lane_value(E, 16);
+        const double s2m = m2 * m3, s2e = __builtin_fma(m2, e3, e2);     // rows 2-3
+        const double s1m = m1 * s2m, s1e = __builtin_fma(m1, s2e, e1);   // rows 1-3
+        const double sm = row == 3 ? 1.0 : row == 2 ? m3 : row == 1 ? s2m : s1m;
+        const double se = row == 3 ? 0.0 : row == 2 ? e3 : row == 1 ? s2e : s1e;
+        E = __builtin_fma(se, M, E);
+        M = sm * M;
     }
 }
 
-// NB = blocks of 64 cells per row (np in (64 (NB - 1), 64 NB]).  V is the
-// storage type of r and z (FP64, or FP32 for the inner iterations of the
-// refined mode); the recurrences always run in FP64.
+// The value at position n - 1 of a register array (0 for n = 0), by a
+// chain of selects (the index is per lane).
+template <int NB>
+__device__ __forceinline__ double t_end(const double (&u)[NB], int n)
+{
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) v = (t == n - 1) ? u[t] : v;
+    return v;
+}
+
+// NB = cells per lane's run, ceil(np / 64) (np in (64 (NB - 1), 64 NB]).  V is
+// the storage type of r and z (FP64, or FP32 for the inner iterations of the
+// refined mode); the recurrences always run in FP64.  LDS: one row per
+// wavefront, cell k at k + k / NB (one slot of padding per run, so that the
+// lanes' strided run accesses spread over the banks).
 template <int NB, typename V>
 __global__ void __launch_bounds__(kThreads)
 line_solve_kernel(GridArgs g, const V *__restrict__ rin, V *__restrict__ zout, double *__restrict__ partial,
@@ -1570,6 +1603,8 @@ line_solve_kernel(GridArgs g, const V *__restrict__ rin, V *__restrict__ zout, d
 {
     const CPtr<const DevScalars> csc = to_const(sc);
     if (!ignore_done && csc->done) return;   // uniform over the workgroup
+    constexpr int kRowSlots = NB * kWave + kWave;
+    __shared__ double rowbuf[kWaves][kRowSlots];
     __shared__ double red[kWaves][2];
     const GPtr<const V> gr = to_global(rin);
     const GPtr<V> gz = to_global(zout);
@@ -1577,77 +1612,119 @@ line_solve_kernel(GridArgs g, const V *__restrict__ rin, V *__restrict__ zout, d
     const int np = g.np;
     const int lane = threadIdx.x & (kWave - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int row16 = lane >> 4, rl = lane & 15;
-    const int nl = np - kWave * (NB - 1);        // cells in the last block (1..64)
-    const bool lane_last = lane < nl;            // this lane holds a cell of the last block
-    const double dph = to_global(g.dphi)[0];     // uniform phi: every width is 2 pi / np
+    double *const row = rowbuf[w];
+    const int n_l = min(NB, max(0, np - lane * NB));   // cells of this lane's run
+    const int run0 = lane * (NB + 1);                  // LDS slot of the run's first cell
+    const int last_lane = (np - 1) / NB;               // the lane that holds cell np - 1
+    const double dph = to_global(g.dphi)[0];           // uniform phi: every width is 2 pi / np
     const double ih = to_global(g.ih)[0];
     const long long nrows = (long long)g.nr * g.nt;
     double acc_rz = 0.0, acc_rr = 0.0;
 
-    for (long long row = (long long)blockIdx.x * kWaves + w; row < nrows; row += (long long)gridDim.x * kWaves) {
-        const RowCoef rc = load_row(crows, CHK(row, nrows));
-        const long long base = row * g.pitch;
-        double rv[NB], u[NB];
+    // r of a row, coalesced (cell 64 q + lane), into registers (storage type)
+    auto load_r = [&](long long rw, V (&rq)[NB]) {
+        const long long base = rw * g.pitch;
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int k = q * kWave + lane;
-            rv[q] = (q < NB - 1 || lane_last) ? (double)stream_load(gr + CHK(base + k, g.npad)) : 0.0;
+            rq[q] = k < np ? stream_load(gr + CHK(base + k, g.npad)) : V(0);
         }
+    };
+    // FP32 storage: the next row's r is loaded under this row's work (the
+    // registers it takes leave the occupancy unchanged there; in FP64 they
+    // would cost a wavefront per SIMD at 601 cells)
+    constexpr bool kPrefetch = sizeof(V) == 4;
+    const long long rstride = (long long)gridDim.x * kWaves;
+    V rq[NB];
+    long long rw = (long long)blockIdx.x * kWaves + w;
+    if (kPrefetch && rw < nrows) load_r(rw, rq);
+    for (; rw < nrows; rw += rstride) {
+        const RowCoef rc = load_row(crows, CHK(rw, nrows));
+        const long long base = rw * g.pitch;
+        if (!kPrefetch) load_r(rw, rq);
+        // r into LDS, then each lane's run into registers
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int k = q * kWave + lane;
+            if (k < np) row[CHK(k + k / NB, kRowSlots)] = (double)rq[q];
+        }
+        if (kPrefetch && rw + rstride < nrows) load_r(rw + rstride, rq);
+        wave_sync();
+        double rv[NB], u[NB];
+#pragma unroll
+        for (int t = 0; t < NB; ++t) rv[t] = t < n_l ? row[CHK(run0 + t, kRowSlots)] : 0.0;
+        wave_sync();
+
         const double wgt = rc.pq * ih;                       // azimuthal weight w
         const double e = dph * rc.s / (2.0 * wgt);           // d / (2 w) - 1 > 0
         const double mu = 1.0 / (1.0 + e + sqrt(e * (2.0 + e)));
-        double mpow[5];                                       // mu, mu^2, mu^4, mu^8, mu^16
-        mpow[0] = mu;
-#pragma unroll
-        for (int t = 1; t < 5; ++t) mpow[t] = mpow[t - 1] * mpow[t - 1];
-        const double mu64 = (mpow[4] * mpow[4]) * (mpow[4] * mpow[4]);
-        const double inv_wrap = 1.0 / (1.0 - powi(mu, np));  // 1 / (1 - mu^np)
-        const double pw_fw = powi(mu, rl + 1);                // mu^(lane % 16 + 1)
-        const double pw_bw = powi(mu, 16 - rl);               // mu^(16 - lane % 16)
+        const double inv_wrap = 1.0 / (1.0 - powi(mu, np)); // 1 / (1 - mu^np)
+        const double m_run = powi(mu, n_l);                  // mu^n_l (1 for an empty run)
 
-        // forward: u_k = r_k + mu u_{k-1}, first without the wrap (u_{-1} = 0)
-        double carry = 0.0, ulast = 0.0;
+        // forward: u_k = r_k + mu u_{k-1}; the run from a zero start
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            acc = __builtin_fma(mu, acc, rv[t]);
+            u[t] = acc;
+        }
+        double M = m_run, E = t_end(u, n_l);
+        affine_scan<true>(M, E, lane);
+        // carry into this run (u at cell l NB - 1, non-periodic) and mu^(l NB)
+        // (lane 0 reads 0 for both; branch-free, as in affine_scan)
+        const double C = shr1(E);
+        const double B = shr1(M) + (lane == 0 ? 1.0 : 0.0);
+        const double ulast = lane_value(E, last_lane);      // u_{np-1}, non-periodic
+        {
+            const double cin = __builtin_fma(B, ulast * inv_wrap, C);   // carry plus the wrap
+            double pw = mu;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                u[t] = t < n_l ? __builtin_fma(pw, cin, u[t]) : 0.0;
+                pw *= mu;
+            }
+        }
+        // backward: v_k = u_k + mu v_{k+1}; the run from a zero end
+        acc = 0.0;
+#pragma unroll
+        for (int t = NB - 1; t >= 0; --t) {
+            acc = __builtin_fma(mu, acc, u[t]);
+            u[t] = acc;
+        }
+        M = m_run;
+        double F = u[0];
+        affine_scan<false>(M, F, lane);
+        // v at cell (l + 1) NB (non-periodic) and mu^(np - (l + 1) NB)
+        // (lane 63 reads 0 for both; branch-free)
+        const double D = shl1(F);
+        const double T = shl1(M) + (lane == kWave - 1 ? 1.0 : 0.0);
+        const double v0 = lane_value(F, 0);                 // v_0, non-periodic
+        const double scale = mu / wgt;
+        {
+            const double din = __builtin_fma(T, v0 * inv_wrap, D);   // carry plus the wrap
+            double pw = mu;
+#pragma unroll
+            for (int t = NB - 1; t >= 0; --t) {
+                if (t < n_l) {
+                    const double z = scale * __builtin_fma(pw, din, u[t]);
+                    u[t] = z;
+                    acc_rz = __builtin_fma(rv[t], z, acc_rz);
+                    acc_rr = __builtin_fma(rv[t], rv[t], acc_rr);
+                    pw *= mu;
+                }
+            }
+        }
+        // z back through LDS to the coalesced layout
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+            if (t < n_l) row[CHK(run0 + t, kRowSlots)] = u[t];
+        wave_sync();
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            u[q] = block_recurrence<true>(rv[q], carry, mpow, pw_fw, row16);
-            if (q == NB - 1) ulast = lane_value(u[q], nl - 1);   // u at cell np - 1
-        }
-        // the wrap: u_{np-1} = ulast / (1 - mu^np) enters cell k as mu^(k+1) u_{np-1}
-        {
-            double f = powi(mu, lane + 1) * (ulast * inv_wrap);
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                u[q] = (q < NB - 1 || lane_last) ? u[q] + f : 0.0;
-                f *= mu64;
-            }
-        }
-        // backward: v_k = u_k + mu v_{k+1}, first without the wrap (v_np = 0)
-        carry = 0.0;
-#pragma unroll
-        for (int q = NB - 1; q >= 0; --q) u[q] = block_recurrence<false>(u[q], carry, mpow, pw_bw, row16);
-        // the wrap: v_0 = carry / (1 - mu^np) enters cell k as mu^(np-k) v_0;
-        // np - k is nl - lane in the last block and 64 more per block before it
-        const double v0 = carry * inv_wrap;
-        const double scale = mu / wgt;
-        double fb = powi(mu, nl - lane + kWave);
-#pragma unroll
-        for (int q = NB - 1; q >= 0; --q) {
             const int k = q * kWave + lane;
-            double fe;
-            if (q == NB - 1) {
-                fe = lane_last ? powi(mu, nl - lane) : 0.0;
-            } else {
-                fe = fb;
-                fb *= mu64;
-            }
-            if (q < NB - 1 || lane_last) {
-                const double z = scale * __builtin_fma(fe, v0, u[q]);
-                stream_store(gz + CHK(base + k, g.npad), (V)z);
-                acc_rz = __builtin_fma(rv[q], z, acc_rz);
-                acc_rr = __builtin_fma(rv[q], rv[q], acc_rr);
-            }
+            if (k < np) stream_store(gz + CHK(base + k, g.npad), (V)row[CHK(k + k / NB, kRowSlots)]);
         }
+        wave_sync();
     }
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) {
@@ -1715,6 +1792,29 @@ template hipError_t launch_line<double>(const GridArgs &, const double *, double
                                         const DevScalars *, int, hipStream_t);
 template hipError_t launch_line<float>(const GridArgs &, const float *, float *, double *, int, const DevScalars *,
                                        int, hipStream_t);
+
+template <int NB, typename V>
+static int line_blocks_per_cu_nb(int nb)
+{
+    if constexpr (NB > 1) {
+        if (nb < NB) return line_blocks_per_cu_nb<NB - 1, V>(nb);
+    }
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&line_solve_kernel<NB, V>),
+                                                     kThreads, 0) != hipSuccess)
+        return 0;
+    return n;
+}
+
+template <typename V>
+int line_blocks_per_cu(int np)
+{
+    const int nb = (np + kWave - 1) / kWave;
+    if (nb < 1 || nb > kMaxLineCells / kWave) return 0;
+    return line_blocks_per_cu_nb<kMaxLineCells / kWave, V>(nb);
+}
+template int line_blocks_per_cu<double>(int);
+template int line_blocks_per_cu<float>(int);
 
 // ---------------------------------------------------------------------------
 // Refinement helpers (pointwise over the padded arrays; padding stays zero).

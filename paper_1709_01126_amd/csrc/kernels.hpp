@@ -92,6 +92,9 @@ constexpr int kMaxLineCells = 32 * 64;
 template <typename V>
 hipError_t launch_line(const GridArgs &g, const V *r, V *z, double *partial, int nblocks, const DevScalars *sc,
                        int ignore_done, hipStream_t s);
+// Workgroups of the line pass resident per CU (0 if unknown).
+template <typename V>
+int line_blocks_per_cu(int np);
 
 // Point Jacobi z = D^-1 r (padded layout).
 hipError_t launch_jacobi(const GridArgs &g, const double *r, double *z, hipStream_t s);
