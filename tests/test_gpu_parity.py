@@ -204,6 +204,27 @@ def test_x_every_other_sweep_matches_every_sweep(case, monkeypatch):
               f"{np.abs(a[0] - b[0]).max() / scale:.1e}", flush=True)
 
 
+def test_x_pairing_falls_back_after_convergence(monkeypatch):
+    """On a 12-unknown grid a fixed-count run goes far past convergence: the
+    residual sits at rounding level, beta becomes tiny or the predicted r.z
+    non-positive (a restart, beta = 0), and the even sweeps must update x
+    themselves instead of leaving a rebuilt increment to the odd ones.  The
+    result must still be the oracle's solution and match the every-sweep form."""
+    rf, tf, pf = make_faces(*GRIDS[0])
+    br = magnetograms.br_bipoles(tf, pf, 3, seed=4)
+    ref = oracle.solve(rf, tf, pf, br, 1e-12, 1000)
+    got = {}
+    for mode in ("2", "1"):
+        monkeypatch.setenv("POT3D_SWEEP_X", mode)
+        with P.Solver(rf, tf, pf) as s:
+            got[mode] = [gpu_solve(s, br, 0.0, K) for K in (40, 41)]
+    for a, b in zip(got["2"], got["1"]):
+        assert a[1] == b[1] == P.ENOCONV and a[2] == b[2]
+        scale = np.abs(ref["phi"]).max()
+        assert np.abs(a[0] - b[0]).max() <= 1e-12 * scale
+        assert np.abs(a[0] - ref["phi"]).max() <= 1e-10 * scale
+
+
 def test_small_workload_parity_and_poles():
     rf, tf, pf = SMALL.faces()
     br = SMALL.br((rf, tf, pf))
