@@ -942,14 +942,17 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih);
     const GPtr<double> gpart = to_global(v.partial);
 
-    // Workgroup -> tile, XCD-aware as in march_body.
+    // Workgroup -> tile, XCD-aware as in march_body, with the radial chunk
+    // outermost: an XCD's range of workgroups then covers twice as many polar
+    // tile rows of one chunk, so fewer tiles have their polar neighbours (whose
+    // rings they read) in another XCD's L2.
     const int per = g.nblocks / kXcds;
     int L = (b < per * kXcds) ? (b % kXcds) * per + b / kXcds : b;
     if (g.reverse) L = g.nblocks - 1 - L;
     const int kt = L % g.ntk;
     L /= g.ntk;
-    const int ic = L % g.nchunk;
-    const int jt = L / g.nchunk;
+    const int jt = L % g.ntj;
+    const int ic = L / g.ntj;
     const int nt = g.nt, np = g.np, nr = g.nr;
     const int i0 = ic * g.ci;
     const int i1 = min(i0 + g.ci, nr);
