@@ -68,6 +68,8 @@ KERNEL_KEYS = {"sweep_even": (32.0, ("stencil_sweep<", "double, 1>")),
                "sweep_odd": (48.0, ("stencil_sweep<", "double, 2>")),
                "sweep": (48.0, ("stencil_sweep<", "double, 0>")),
                "update_p": (24.0, (", 2, double>",)), "update_r": (40.0, (", 3, double>",)),
+               # the r/x update of the two-pass and phi-line iterations, x once per pair
+               "update_r_skip": (24.0, (", 4, double>",)), "update_r_pair": (48.0, (", 5, double>",)),
                "sweep_fp32_even": (16.0, ("stencil_sweep<", "float, 1>")),
                "sweep_fp32_odd": (24.0, ("stencil_sweep<", "float, 2>")),
                "line": (16.0, ("line_solve_kernel<",))}
@@ -623,7 +625,8 @@ def main():
     else:
         kern = {
             "update_p": {"alg_bytes_per_launch": KERNEL_KEYS["update_p"][0] * w.n, "ms": ms_a},
-            "update_r": {"alg_bytes_per_launch": KERNEL_KEYS["update_r"][0] * w.n, "ms": ms_b},
+            # the r/x update's mean over a pair of iterations (x once per pair: 24 N and 48 N)
+            "update_r": {"alg_bytes_per_launch": (bytes_iter / w.n - KERNEL_KEYS["update_p"][0]) * w.n, "ms": ms_b},
         }
     for k, v in kern.items():
         v["gbs"] = v["alg_bytes_per_launch"] / (v["ms"] * 1e-3) / 1e9
@@ -737,7 +740,8 @@ def main():
             "solve_s": round(tl, 4), "speedup_vs_point_jacobi": round(result["fp64_solve_s"] / tl, 3),
             "iters": itl, "iters_point_jacobi": result["config"]["iters_per_solve"],
             "iters_per_s": round(itl / tl, 2), "loop_us_per_iter": round(sl["loop_ms"] * 1e3 / max(1, itl), 2),
-            "gbs_alg_80N": round(80.0 * w.n * itl / (sl["loop_ms"] * 1e-3) / 1e9, 1),
+            "bytes_per_unknown": round(sl["bytes_per_iter"] / w.n, 3),
+            "gbs_alg": round(sl["bytes_per_iter"] * itl / (sl["loop_ms"] * 1e-3) / 1e9, 1),
             "status": pot3d.STATUS_NAMES.get(stl, stl), "relres_true": rrl,
             "max_rel_err_vs_oracle_samples": err_vs_samples(torch, d_phi_l, golden_samples(w.name + "_phi_line")),
             "max_rel_diff_vs_point_jacobi": float(torch.max(torch.abs(d_phi_l - d_phi)).item()

@@ -75,7 +75,9 @@ enum pot3d_refine_mode {
 enum pot3d_iteration {
     POT3D_ITER_TWO_PASS = 0,   /* two sweeps over memory per PCG iteration: the direction
                                   update with A p and p.Ap, then the r/x update with r.z and
-                                  r.r (64 bytes per unknown)                                 */
+                                  r.r; x once per pair of iterations (the odd r/x update
+                                  reads p_{k-1}): 60 bytes per unknown on average, 64 with
+                                  POT3D_SWEEP_X=1                                             */
     POT3D_ITER_ONE_SWEEP = 1   /* one sweep per iteration: the r/x update of iteration j-1
                                   and the direction update of iteration j together, with
                                   r.z of the next residual predicted from p.Ap, z.Ap and
@@ -113,11 +115,11 @@ typedef struct pot3d_stats {
     double relres_true;      /* ||b - A Phi||/||b||, recomputed in FP64 at exit             */
     double solve_ms;         /* wall time of the last solve call on the device             */
     double loop_ms;          /* device time of the iteration loop (hipEvents)               */
-    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration: 40 N (FP64, one
-                                sweep, x every other sweep; 48 N with x every sweep), 64 N
-                                (FP64, two passes), 80 N (FP64, phi-line preconditioner),
-                                20 N (24 N) / 32 N / 40 N (FP32 inner: one sweep / two
-                                passes / phi-line)                                         */
+    double bytes_per_iter;   /* algorithmic HBM bytes of one iteration, x once per pair of
+                                iterations (with POT3D_SWEEP_X=1, x every iteration): FP64
+                                40 N (48 N) one sweep, 60 N (64 N) two passes, 76 N (80 N)
+                                with the phi-line preconditioner; FP32 inner iterations
+                                half of each                                               */
     long long n;             /* unknowns nr*nt*np                                            */
     int pitch;               /* row pitch (elements) of the internal phi-fastest arrays    */
     int tile_p, tile_r;      /* stencil kernel shape of the p update and of the r/x update:
@@ -291,8 +293,8 @@ int pot3d_set_iteration(pot3d_ctx *ctx, int iteration);
  *                      line pass that solves the rows (one wavefront per row:
  *                      the circulant block of a uniform phi grid factors
  *                      into two first-order periodic recurrences, always
- *                      evaluated in FP64) and writes z: 80 bytes per unknown
- *                      per FP64 iteration (40 per FP32 one) against 40 or 64
+ *                      evaluated in FP64) and writes z: 76 bytes per unknown
+ *                      per FP64 iteration (38 per FP32 one) against 40 or 60
  *                      for point Jacobi, for fewer iterations.  Allocates one
  *                      more vector (8 N or 4 N bytes) on first use.
  * POT3D_EINVAL (nothing changed) unless the context's phi faces are uniform

@@ -427,9 +427,10 @@ int capture_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, DevScalars *sc, h
             bv.sc = sc;
             bv.partial = c->partial;
             bv.in = pb[(it + 1) & 1];
+            bv.pold = pb[it & 1];   // p_{k-1}, for the odd r/x update of a pair
             bv.r = r;
             bv.x = x;
-            e = launch_stencil<V>(kUpdateR, c->tile_r, c->grid_r, bv, s);
+            e = launch_stencil<V>(update_r_mode(it, c->graph_m), c->tile_r, c->grid_r, bv, s);
         }
         if (e == hipSuccess) e = launch_finish(kFinRho, sc, c->partial, c->grid_r.nblocks, s);
     }
@@ -461,6 +462,22 @@ int sweep_xmode(int it)
 double sweep_bytes(bool fp32)
 {
     const double b = env_int("POT3D_SWEEP_X", 2) == 1 ? 48.0 : 40.0;
+    return fp32 ? b / 2 : b;
+}
+
+// The two-pass form pairs its iterations the same way: the even r/x update
+// leaves x alone (24 N instead of 40 N), the odd one reads p_{k-1} and adds
+// both increments (48 N).  Only for an even number of captured iterations, so
+// that replays continue the alternation.
+int update_r_mode(int it, int m)
+{
+    if (env_int("POT3D_SWEEP_X", 2) == 1 || (m & 1)) return kUpdateR;
+    return (it & 1) ? kUpdateRPair : kUpdateRSkip;
+}
+
+double two_pass_bytes(bool fp32, int m)
+{
+    const double b = update_r_mode(0, m) == kUpdateR ? 64.0 : 60.0;
     return fp32 ? b / 2 : b;
 }
 
@@ -529,10 +546,11 @@ int capture_line_iterations(pot3d_ctx *c, V *r, V *p0, V *p1, V *x, V *z, DevSca
             bv.sc = sc;
             bv.partial = c->partial;
             bv.in = pb[(it + 1) & 1];
+            bv.pold = pb[it & 1];   // p_{k-1}, for the odd r/x update of a pair
             bv.r = r;
             bv.x = x;
             bv.zin = 1;
-            e = launch_stencil<V>(kUpdateR, c->tile_r, c->grid_r, bv, s);
+            e = launch_stencil<V>(update_r_mode(it, c->graph_m), c->tile_r, c->grid_r, bv, s);
         }
         if (e == hipSuccess) e = launch_line<V>(c->grid_o, r, z, c->partial, c->line_blocks, sc, 0, s);
         if (e == hipSuccess) e = launch_finish(kFinRho, sc, c->partial, c->line_blocks, s);
@@ -689,10 +707,10 @@ int run_fp64(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream_t 
     hipGraphExec_t graph = line ? c->graph_l : (sweep ? c->graph_s : c->graph);
     rc = replay_until_done(c, graph, c->sc, s, maxit, sweep ? 2 * c->graph_m : c->graph_m, &launches, &fin);
     if (rc != POT3D_OK) return rc;
-    // the increment of x the last sweep may have left to a next one
-    if (sweep) HIP_TRY(c, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, s));
+    // the increment of x the last sweep or r/x update may have left to a next one
+    HIP_TRY(c, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, s));
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, line ? 80.0 : (sweep ? sweep_bytes(false) : 64.0), iters,
+    return finish_solve(c, phi_out, kind_out, s, fin, launches, fin.k, 1, line ? two_pass_bytes(false, c->graph_m) + 16.0 : (sweep ? sweep_bytes(false) : two_pass_bytes(false, c->graph_m)), iters,
                         relres_true);
 }
 
@@ -810,7 +828,7 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         rc = replay_until_done(c, line ? c->graph32l : (sweep ? c->graph32s : c->graph32), c->sc32, s, maxit - total,
                                sweep ? 2 * c->graph_m : c->graph_m, &launches, &inner);
         if (rc != POT3D_OK) return rc;
-        if (sweep) HIP_TRY(c, launch_x_catchup<float>(c->e32, c->sc32, c->nr, c->nt, c->np, c->pitch, s));
+        HIP_TRY(c, launch_x_catchup<float>(c->e32, c->sc32, c->nr, c->nt, c->np, c->pitch, s));
         total += inner.k;
         ++outer;
         if (inner.status == POT3D_EBREAKDOWN) {
@@ -821,7 +839,8 @@ int run_refined(pot3d_ctx *c, double *phi_out, hipMemcpyKind kind_out, hipStream
         if (rc != POT3D_OK) return rc;
     }
     HIP_TRY(c, hipEventRecord(c->ev_loop1, s));
-    const double per = c->precond == POT3D_PC_PHI_LINE ? 40.0 : (one_sweep(c) ? sweep_bytes(true) : 32.0);
+    const double per = c->precond == POT3D_PC_PHI_LINE ? two_pass_bytes(true, c->graph_m) + 8.0
+                                                       : (one_sweep(c) ? sweep_bytes(true) : two_pass_bytes(true, c->graph_m));
     return finish_solve(c, phi_out, kind_out, s, out, launches, total, outer, per, iters, relres_true);
 }
 
@@ -910,7 +929,7 @@ template <typename V>
 int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps, double *ms_p, double *ms_r)
 {
     hipStream_t s = ctx->stream;
-    const int m = std::max(1, reps);
+    const int m = std::max(2, reps + (reps & 1));   // even: the r/x updates pair up, across the two replays too
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess || khz <= 0)
         return fail(ctx, POT3D_EDEVICE, "device wall-clock rate unavailable");
@@ -954,13 +973,14 @@ int time_pair(pot3d_ctx *ctx, V *r, V *p0, V *p1, V *x, DevScalars *sc, int reps
         bv.sc = sc;
         bv.partial = ctx->partial;
         bv.in = pb[(it + 1) & 1];
+        bv.pold = pb[it & 1];
         bv.r = r;
         bv.x = x;
         bv.ignore_done = 1;
         bv.tstamp = d_ts + 4 * it + 2;
         e = launch_stencil<V>(kUpdateP, ctx->tile_p, ctx->grid_p, a, s);
         if (e == hipSuccess) e = launch_finish(kFinSigma, sc, ctx->partial, ctx->grid_p.nblocks, s);
-        if (e == hipSuccess) e = launch_stencil<V>(kUpdateR, ctx->tile_r, ctx->grid_r, bv, s);
+        if (e == hipSuccess) e = launch_stencil<V>(update_r_mode(it, m), ctx->tile_r, ctx->grid_r, bv, s);
         if (e == hipSuccess) e = launch_finish(kFinRho, sc, ctx->partial, ctx->grid_r.nblocks, s);
     }
     hipGraph_t graph = nullptr;
@@ -1402,8 +1422,8 @@ int pot3d_get_stats(const pot3d_ctx *ctx, pot3d_stats *out)
     out->pitch = ctx->pitch;
     fill_shape(ctx, *out);
     const bool fp32 = ctx->precision == POT3D_FP32_REFINED;
-    const double per = ctx->precond == POT3D_PC_PHI_LINE ? (fp32 ? 40.0 : 80.0)
-                       : one_sweep(ctx) ? sweep_bytes(fp32) : (fp32 ? 32.0 : 64.0);
+    const double per = ctx->precond == POT3D_PC_PHI_LINE ? two_pass_bytes(fp32, ctx->graph_m) + (fp32 ? 8.0 : 16.0)
+                       : one_sweep(ctx) ? sweep_bytes(fp32) : two_pass_bytes(fp32, ctx->graph_m);
     out->bytes_per_iter = per * (double)ctx->n;
     return POT3D_OK;
 }

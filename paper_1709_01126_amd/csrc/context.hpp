@@ -139,6 +139,11 @@ GridArgs make_sweep_grid(const pot3d_ctx *c, int rows, int target);
 // the HBM bytes per unknown per iteration of the one-sweep form that go with it.
 int sweep_xmode(int it);
 double sweep_bytes(bool fp32);
+// The r/x update mode of iteration `it` of a captured sequence of m two-pass
+// (or phi-line) iterations, and the bytes per unknown of a two-pass iteration
+// that go with it (the phi-line iteration adds 16 N, 8 N in FP32).
+int update_r_mode(int it, int m);
+double two_pass_bytes(bool fp32, int m);
 // Allocate a context on `device` (tables, vectors, graphs).  serving = true:
 // no graph capture (the server's batched graph iterates it).
 int create_context(const double *rf, int nr, const double *tf, int nt, const double *pf, int np, int upper_bc,

@@ -111,6 +111,19 @@ __device__ __forceinline__ V diag_at(const RowCoef &rc, V dph, V ihm, V ihk)
     return vfma<V>(dph, (V)rc.s, (V)rc.pq * (ihm + ihk));
 }
 
+// The r/x update in pairs of iterations: the even one records the increment
+// x still lacks (alpha_k p_k: the scalar and the buffer of p_k), which a
+// catch-up adds if the solve ends after it; the other r/x updates clear it.
+template <int MODE, typename V>
+__device__ __forceinline__ void record_x_lag(const DevScalars *sc, CPtr<const DevScalars> csc, const V *p, int b)
+{
+    if (is_update_r(MODE) && b == 0 && threadIdx.x == 0) {
+        DevScalars *w = const_cast<DevScalars *>(sc);
+        w->x_lag = MODE == kUpdateRSkip ? csc->alpha : 0.0;
+        w->x_lag_p = MODE == kUpdateRSkip ? (unsigned long long)p : 0ull;
+    }
+}
+
 // The LDS-plane marching pass for one workgroup; b is the workgroup's index
 // within its own launch shape (blockIdx.x for a single solve, the index inside
 // the slot for a batched launch).
@@ -198,9 +211,11 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
         hihk = (V)gih[CHK(hk, np)];
     }
 
-    V beta = 0, alpha = 0;
+    V beta = 0, alpha = 0, alpha_p = 0;
     if (MODE == kUpdateP) beta = (V)csc->beta;
-    if (MODE == kUpdateR) alpha = (V)csc->alpha;
+    if (is_update_r(MODE)) alpha = (V)csc->alpha;
+    if (MODE == kUpdateRPair) alpha_p = (V)csc->alpha_prev;
+    record_x_lag<MODE>(v.sc, csc, vin, b);
 
     auto offs = [&](int ip, int j, int kk) -> long long {
         return (long long)ip * g.plane + (long long)j * g.pitch + kk;
@@ -271,16 +286,17 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
 
     for (int i = i0; i < i1; ++i) {
         // this layer's r and x (update-r), issued with the next layer's operand
-        V rv[M], xv[M];
+        V rv[M], xv[M], pv[M];
         RowCoef rc[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int jc = min(j0 + w + kWaves * m, nt - 1);
             rc[m] = load_row(crows, CHK(i * nt + jc, nr * nt));
-            if constexpr (MODE == kUpdateR) {
+            if constexpr (is_update_r(MODE)) {
                 const long long o = CHK(offs(i, jc, kc), g.npad);
                 rv[m] = stream_load(gout + o);
-                xv[m] = stream_load(gout2 + o);
+                if constexpr (MODE != kUpdateRSkip) xv[m] = stream_load(gout2 + o);
+                if constexpr (MODE == kUpdateRPair) pv[m] = stream_load(gpold + o);   // p_{k-1}
             }
         }
         produce(i + 1, i + 1 < nr, (i + 1) % 3, q2, true, MODE == kUpdateP && i + 1 < i1);
@@ -326,7 +342,9 @@ __device__ __forceinline__ void march_body(const GridArgs &g, const StencilVecs<
                 if (on) {
                     const V rn = vfma<V>(-alpha, ap, rv[m]);
                     stream_store(gout + idx, rn);
-                    stream_store(gout2 + idx, vfma<V>(alpha, pc, xv[m]));
+                    if constexpr (MODE == kUpdateR) stream_store(gout2 + idx, vfma<V>(alpha, pc, xv[m]));
+                    if constexpr (MODE == kUpdateRPair)
+                        stream_store(gout2 + idx, vfma<V>(alpha, pc, vfma<V>(alpha_p, pv[m], xv[m])));
                     if (!v.zin) {   // with a block preconditioner the line pass takes r.z and r.r
                         const V z = rn / diag_at<V>(r_, dph, ihm, ihk);
                         acc0 += (double)rn * (double)z;
@@ -480,6 +498,7 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
     const CPtr<const RowCoef> crows = to_const(rows);
     if (!v.ignore_done && csc->done) return;   // uniform over the workgroup
     if (v.tstamp && threadIdx.x == 0) atomicMin(&v.tstamp[0], wall_clock64());
+    record_x_lag<MODE>(v.sc, csc, vin, b);
     const GPtr<const V> gin = to_global(vin), gpold = to_global(vpold);
     const GPtr<V> gout = to_global(vout), gout2 = to_global(vout2);
     const GPtr<const double> gdphi = to_global(g.dphi), gih = to_global(g.ih), gbp = to_global(v.bplane);
@@ -523,7 +542,8 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
         const V dphl = (V)gdphi[CHK(kl, np)], ihml = (V)gih[CHK(kl == 0 ? np - 1 : kl - 1, np)], ihkl = (V)gih[CHK(kl, np)];
         const V dphr = (V)gdphi[CHK(kr, np)], ihmr = (V)gih[CHK(kr == 0 ? np - 1 : kr - 1, np)], ihkr = (V)gih[CHK(kr, np)];
         const V beta = (MODE == kUpdateP) ? (V)csc->beta : V(0);
-        const V alpha = (MODE == kUpdateR) ? (V)csc->alpha : V(0);
+        const V alpha = is_update_r(MODE) ? (V)csc->alpha : V(0);
+        const V alpha_p = (MODE == kUpdateRPair) ? (V)csc->alpha_prev : V(0);
 
         auto rowoff = [&](int ip, int j) -> long long { return (long long)ip * g.plane + (long long)j * g.pitch; };
         auto ld2 = [&](GPtr<const V> p, long long off) -> P2 { return *(GPtr<const P2>)(p + CHK(off, g.npad - 1)); };
@@ -588,7 +608,7 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
             o.x = v0 ? a0 : V(0);
             o.y = v1 ? a1 : V(0);
             GPtr<P2> to = (GPtr<P2>)(dst + CHK(rowoff(ip, j) + kc, g.npad - 1));
-            if constexpr (MODE == kUpdateP || MODE == kUpdateR) {
+            if constexpr (MODE == kUpdateP || is_update_r(MODE)) {
                 if (lane_on) stream_store(to, o);
             } else {
                 if (lane_on) *to = o;
@@ -625,7 +645,7 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
             Raw nxt[M], hraw[2];
             RawCell cl[M], cr[M];
             RowCoef rc[M], rcn[M], rch[2];
-            P2 rv[M], xv[M];
+            P2 rv[M], xv[M], pv[M];
 #pragma unroll
             for (int m = 0; m < M; ++m) {
                 const int jc = min(j0 + m, nt - 1);
@@ -634,9 +654,10 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
                 if constexpr (MODE == kUpdateP) rcn[m] = load_row(crows, CHK(ipn * nt + jc, nr * nt));
                 cl[m] = raw_cell(i, jc, kl);
                 cr[m] = raw_cell(i, jc, kr);
-                if constexpr (MODE == kUpdateR) {
+                if constexpr (is_update_r(MODE)) {
                     rv[m] = ld2_stream(gout, rowoff(i, jc) + kc);
-                    xv[m] = ld2_stream(gout2, rowoff(i, jc) + kc);
+                    if constexpr (MODE != kUpdateRSkip) xv[m] = ld2_stream(gout2, rowoff(i, jc) + kc);
+                    if constexpr (MODE == kUpdateRPair) pv[m] = ld2_stream(gpold, rowoff(i, jc) + kc);   // p_{k-1}
                 }
             }
             hraw[0] = raw_row(i, jlo, false);
@@ -707,8 +728,17 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
                     if (v.store_r && row_on) store2(gout, i, j, res[0], res[1]);
                 } else if constexpr (MODE == kUpdateP) {
                     acc0 += wrow * ((double)c0 * (double)ap[0] + (double)c1 * (double)ap[1]);
-                } else {  // kUpdateR
-                    const V rr[2] = {rv[m].x, rv[m].y}, xx[2] = {xv[m].x, xv[m].y};
+                } else {  // the r/x update modes
+                    const V rr[2] = {rv[m].x, rv[m].y};
+                    V xx[2] = {V(0), V(0)};
+                    if constexpr (MODE != kUpdateRSkip) {
+                        xx[0] = xv[m].x;
+                        xx[1] = xv[m].y;
+                    }
+                    if constexpr (MODE == kUpdateRPair) {   // alpha_{k-1} p_{k-1} first
+                        xx[0] = vfma<V>(alpha_p, pv[m].x, xx[0]);
+                        xx[1] = vfma<V>(alpha_p, pv[m].y, xx[1]);
+                    }
                     V rn[2], xn[2];
 #pragma unroll
                     for (int e = 0; e < 2; ++e) {
@@ -722,7 +752,7 @@ __device__ __forceinline__ void wave_body(const GridArgs &g, const StencilVecs<V
                     }
                     if (row_on) {
                         store2(gout, i, j, rn[0], rn[1]);
-                        store2(gout2, i, j, xn[0], xn[1]);
+                        if constexpr (MODE != kUpdateRSkip) store2(gout2, i, j, xn[0], xn[1]);
                     }
                 }
             }
@@ -1315,12 +1345,14 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
         }
     } else if (which == kFinSigma) {
         // alpha = rho / p.Ap; a non-positive or non-finite curvature ends the solve.
+        // The previous alpha is kept for the r/x update that pairs two iterations.
         const double sigma = s[0];
         sc->sigma = sigma;
         if (!(sigma > 0.0) || !isfinite(sigma)) {
             sc->status = POT3D_EBREAKDOWN;
             sc->done = 1;
         } else {
+            sc->alpha_prev = sc->alpha;
             sc->alpha = sc->rho / sigma;
         }
     } else if (which == kFinRho) {
@@ -2178,6 +2210,8 @@ static hipError_t launch_tj(int mode, const GridArgs &g, const StencilVecs<V> &v
     case kResidual: return launch_kernel(stencil_march<TJ, kResidual, V>, g, v, out, s, e0, e1);
     case kUpdateP: return launch_kernel(stencil_march<TJ, kUpdateP, V>, g, v, out, s, e0, e1);
     case kUpdateR: return launch_kernel(stencil_march<TJ, kUpdateR, V>, g, v, out, s, e0, e1);
+    case kUpdateRSkip: return launch_kernel(stencil_march<TJ, kUpdateRSkip, V>, g, v, out, s, e0, e1);
+    case kUpdateRPair: return launch_kernel(stencil_march<TJ, kUpdateRPair, V>, g, v, out, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -2192,6 +2226,8 @@ static hipError_t launch_wave(int mode, const GridArgs &g, const StencilVecs<V> 
     case kResidual: return launch_kernel(stencil_wave<M, kResidual, V>, g, v, out, s, e0, e1);
     case kUpdateP: return launch_kernel(stencil_wave<M, kUpdateP, V>, g, v, out, s, e0, e1);
     case kUpdateR: return launch_kernel(stencil_wave<M, kUpdateR, V>, g, v, out, s, e0, e1);
+    case kUpdateRSkip: return launch_kernel(stencil_wave<M, kUpdateRSkip, V>, g, v, out, s, e0, e1);
+    case kUpdateRPair: return launch_kernel(stencil_wave<M, kUpdateRPair, V>, g, v, out, s, e0, e1);
     default: return hipErrorInvalidValue;
     }
 }
@@ -2220,6 +2256,8 @@ static const void *stencil_symbol(int mode, int tile)
     case kResidual: return reinterpret_cast<const void *>(&K<T, kResidual, V>);                          \
     case kUpdateP: return reinterpret_cast<const void *>(&K<T, kUpdateP, V>);                            \
     case kUpdateR: return reinterpret_cast<const void *>(&K<T, kUpdateR, V>);                            \
+    case kUpdateRSkip: return reinterpret_cast<const void *>(&K<T, kUpdateRSkip, V>);                    \
+    case kUpdateRPair: return reinterpret_cast<const void *>(&K<T, kUpdateRPair, V>);                    \
     default: return nullptr;                                                                             \
     }
     switch (tile) {
@@ -2321,6 +2359,8 @@ hipError_t launch_march_batch(int mode, const BatchSlot<V> *slots, int nslots, d
     switch (mode) {
     case kUpdateP: stencil_march_batch<TJ, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
     case kUpdateR: stencil_march_batch<TJ, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateRSkip: stencil_march_batch<TJ, kUpdateRSkip, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateRPair: stencil_march_batch<TJ, kUpdateRPair, V><<<grid, block, 0, s>>>(slots, nslots); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -2333,6 +2373,8 @@ hipError_t launch_wave_batch(int mode, const BatchSlot<V> *slots, int nslots, di
     switch (mode) {
     case kUpdateP: stencil_wave_batch<M, kUpdateP, V><<<grid, block, 0, s>>>(slots, nslots); break;
     case kUpdateR: stencil_wave_batch<M, kUpdateR, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateRSkip: stencil_wave_batch<M, kUpdateRSkip, V><<<grid, block, 0, s>>>(slots, nslots); break;
+    case kUpdateRPair: stencil_wave_batch<M, kUpdateRPair, V><<<grid, block, 0, s>>>(slots, nslots); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -189,7 +189,8 @@ int capture_batched(pot3d_server *sv, BatchSlot<V> *const *dp, BatchSlot<V> *con
     for (int it = 0; !sv->sweep && it < sv->graph_m && e == hipSuccess; ++it) {
         e = launch_stencil_batch<V>(kUpdateP, sv->tile_p, dp[it & 1], sv->max_slots, wp, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinSigma, sv->d_finp, sv->max_slots, s);
-        if (e == hipSuccess) e = launch_stencil_batch<V>(kUpdateR, sv->tile_r, dr[it & 1], sv->max_slots, wr, s);
+        if (e == hipSuccess)
+            e = launch_stencil_batch<V>(update_r_mode(it, sv->graph_m), sv->tile_r, dr[it & 1], sv->max_slots, wr, s);
         if (e == hipSuccess) e = launch_finish_batch(kFinRho, sv->d_finr, sv->max_slots, s);
     }
     hipGraph_t graph = nullptr;
@@ -305,6 +306,7 @@ void fill_tables(pot3d_server *sv, std::vector<BatchSlot<V>> *hp, std::vector<Ba
             BatchSlot<V> &b = hr[par][q];
             b.g = c->grid_r;
             b.v.in = p[par ^ 1];
+            b.v.pold = p[par];   // p_{k-1}, for the r/x update that pairs two iterations
             b.v.r = r;
             b.v.x = x;
             b.v.sc = sc;
@@ -444,10 +446,10 @@ int retire(pot3d_server *sv, Slot &sl, DevScalars fin, int total_iters, int oute
     double rel = 0.0;
     SV_TRY(sv, hipEventRecord(c->ev_loop1, sv->stream));
     const bool fp32 = sv->precision == POT3D_FP32_REFINED;
-    const double per_unknown = sv->sweep ? sweep_bytes(fp32) : (fp32 ? 32.0 : 64.0);
+    const double per_unknown = sv->sweep ? sweep_bytes(fp32) : two_pass_bytes(fp32, sv->graph_m);
     // the x increment the slot's last sweep may have left (FP64; refined
     // slots caught up their correction before the outer test)
-    if (sv->sweep && !fp32) SV_TRY(sv, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, sv->stream));
+    if (!fp32) SV_TRY(sv, launch_x_catchup<double>(c->x, c->sc, c->nr, c->nt, c->np, c->pitch, sv->stream));
     const int rc = finish_solve(c, dst, hipMemcpyDeviceToHost, sv->stream, fin, sl.launches, total_iters, outer,
                                 per_unknown, &iters, &rel);
     if (rc != POT3D_OK && rc != POT3D_ENOCONV && rc != POT3D_EBREAKDOWN) return sfail(sv, rc, pot3d_last_error(c));
@@ -680,9 +682,8 @@ int pot3d_server_step(pot3d_server *sv, int *n_active, int *n_queued, long long 
                 if (rc != POT3D_OK) return rc;
                 continue;
             }
-            if (sv->sweep)
-                SV_TRY(sv, launch_x_catchup<float>(sl.ctx->e32, sl.ctx->sc32, sl.ctx->nr, sl.ctx->nt, sl.ctx->np,
-                                                   sl.ctx->pitch, s));
+            SV_TRY(sv, launch_x_catchup<float>(sl.ctx->e32, sl.ctx->sc32, sl.ctx->nr, sl.ctx->nt, sl.ctx->np,
+                                               sl.ctx->pitch, s));
             SV_CALL(sv, sl.ctx, refined_correct(sl.ctx, s));
             const int rc = refined_advance(sv, sl);
             if (rc != POT3D_OK) return rc;

@@ -73,13 +73,21 @@ enum Mode : int {
     kApply = 0,   // y = A x
     kResidual = 1,// r = b - A x (optional store); partials r.z, r.r, b.b
     kUpdateP = 2, // p = D^-1 r + beta p_old (stored); partial p.Ap
-    kUpdateR = 3  // r -= alpha A p; x += alpha p; partials r.z, r.r
+    kUpdateR = 3, // r -= alpha A p; x += alpha p; partials r.z, r.r
+    // The r/x update in pairs of iterations (x once per pair): the even one
+    // leaves x alone; the odd one adds both increments,
+    // x += alpha_{k-1} p_{k-1} + alpha_k p_k, reading p_{k-1} (StencilVecs::pold).
+    kUpdateRSkip = 4,
+    kUpdateRPair = 5
 };
+
+// The modes of the r/x update.
+constexpr bool is_update_r(int mode) { return mode == kUpdateR || mode == kUpdateRSkip || mode == kUpdateRPair; }
 
 template <typename V>
 struct StencilVecs {
     const V *in;      // operand: x (apply, residual), p (update-r), r (update-p)
-    const V *pold;    // update-p: previous search direction
+    const V *pold;    // update-p: previous search direction; kUpdateRPair: p_{k-1}
     V *pnew;          // update-p: new search direction (stored)
     V *r;             // residual: out; update-r: in/out
     V *x;             // update-r: in/out

@@ -110,7 +110,8 @@ def test_line_pcg_solve_matches_oracle(case):
     print(f"[line] {label(case)}: gpu {it} iterations, oracle {ref['iters']} (point Jacobi {jac['iters']}), "
           f"true relres {rr:.2e}", flush=True)
     assert st == P.OK and ref["status"] == oracle.OK
-    assert stats["precond"] == P.PC_PHI_LINE and stats["bytes_per_iter"] == 80.0 * phi.size
+    # p update 24 N, r/x update 24 N and 48 N in turn (x once per pair), line pass 16 N
+    assert stats["precond"] == P.PC_PHI_LINE and stats["bytes_per_iter"] == 76.0 * phi.size
     assert iters_close(it, ref["iters"]), (it, ref["iters"])
     x = ref["phi"]
     assert np.linalg.norm(phi - x) <= 1e-8 * np.linalg.norm(x)
@@ -243,6 +244,6 @@ def test_refined_with_line_preconditioner(case):
     print(f"[line refined] {label(case)}: {it} inner iterations in {stats['outer']} outer (FP64 line "
           f"{ref['iters']}), true relres {tr:.2e}, rel err {err:.2e}", flush=True)
     assert st == P.OK and tr <= tol * 1.01
-    assert stats["bytes_per_iter"] == 40.0 * phi.size
+    assert stats["bytes_per_iter"] == 38.0 * phi.size
     assert err <= 1e-7
     assert it <= 2 * ref["iters"] + 64

@@ -154,8 +154,8 @@ def test_solve_matches_oracle(case, iteration):
     print(f"[solve] {label(case)} iteration={iteration} iters gpu={it} oracle={ref['iters']} "
           f"true_relres={rr:.2e}", flush=True)
     assert stats["iteration"] == iteration
-    # one sweep: r and p read and written every sweep, x every other sweep
-    assert stats["bytes_per_iter"] == (40.0 if iteration == P.ITER_ONE_SWEEP else 64.0) * stats["n"]
+    # x once per pair of iterations: one sweep 32 N and 48 N in turn; two passes 24 N + (24 N or 48 N)
+    assert stats["bytes_per_iter"] == (40.0 if iteration == P.ITER_ONE_SWEEP else 60.0) * stats["n"]
     assert st == P.OK and ref["status"] == oracle.OK
     assert iters_close(it, ref["iters"]), (it, ref["iters"])
     check_solution(phi, ref["phi"])
@@ -201,6 +201,34 @@ def test_x_every_other_sweep_matches_every_sweep(case, monkeypatch):
         scale = np.abs(b[0]).max()
         assert np.abs(a[0] - b[0]).max() <= 1e-13 * scale, (K, np.abs(a[0] - b[0]).max() / scale)
         print(f"[x pairing] {label(case)} K={K} iters={a[2]} max diff/max|Phi| = "
+              f"{np.abs(a[0] - b[0]).max() / scale:.1e}", flush=True)
+
+
+@pytest.mark.parametrize("case", [GRIDS[4], GRIDS[6]], ids=label)
+@pytest.mark.parametrize("form", ["two_pass", "phi_line"])
+def test_x_pairs_in_the_two_pass_and_line_forms(case, form, monkeypatch):
+    """The two-pass iteration (and the phi-line one, which runs its r/x update)
+    also updates x once per pair: the even r/x update leaves x alone and the odd
+    one adds alpha_{k-1} p_{k-1} + alpha_k p_k, reading p_{k-1}.  Against the form
+    that updates x every time: the same r and p, iteration counts and statuses,
+    x within rounding; runs ending after an even and after an odd iteration."""
+    rf, tf, pf = make_faces(*case)
+    br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
+    runs = [(0.0, 1), (0.0, 2), (0.0, 17), (0.0, 50), (1e-10, 100_000)]
+    line_bytes = 16.0 if form == "phi_line" else 0.0
+    got = {}
+    for mode in ("2", "1"):
+        monkeypatch.setenv("POT3D_SWEEP_X", mode)
+        with P.Solver(rf, tf, pf, iteration=P.ITER_TWO_PASS) as s:
+            if form == "phi_line":
+                s.set_preconditioner(P.PC_PHI_LINE)
+            got[mode] = [gpu_solve(s, br, tol, K) for tol, K in runs]
+            assert s.stats()["bytes_per_iter"] == ((60.0 if mode == "2" else 64.0) + line_bytes) * s.stats()["n"]
+    for (tol, K), a, b in zip(runs, got["2"], got["1"]):
+        assert a[1] == b[1] and a[2] == b[2], (K, a[1:3], b[1:3])
+        scale = np.abs(b[0]).max()
+        assert np.abs(a[0] - b[0]).max() <= 1e-13 * scale, (K, np.abs(a[0] - b[0]).max() / scale)
+        print(f"[x pairing, {form}] {label(case)} K={K} iters={a[2]} max diff/max|Phi| = "
               f"{np.abs(a[0] - b[0]).max() / scale:.1e}", flush=True)
 
 
