@@ -724,8 +724,8 @@ def main():
         del d_phi_cw
     if not args.no_line:
         # the phi-line block preconditioner on the same grid and data: fewer
-        # iterations, 80 N bytes each (direction update on z, r/x update,
-        # line pass)
+        # iterations, 76 N bytes each on average (direction update on z, r/x
+        # update with x once per pair, line pass)
         solver.set_preconditioner(pot3d.PC_PHI_LINE)
         d_phi_l = torch.empty_like(d_phi)
         stl, itl, rrl = solver.solve_device(d_br, d_phi_l, w.tol, maxit)
