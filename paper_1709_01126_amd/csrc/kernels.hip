@@ -1267,15 +1267,30 @@ constexpr int kFinThreads = 256;
 __device__ __forceinline__ void block_sums(const double *partial, int nb, int ncomp, double out[kMaxPartials])
 {
     // Fixed order: each thread sums its strided partials, a wavefront
-    // butterfly combines the 64 lanes, then the 4 wavefronts in order.
+    // butterfly combines the 64 lanes, then the 4 wavefronts in order.  The
+    // partials were written by workgroups on every XCD, so each read misses
+    // this XCD's L2: a thread issues the loads of kFinLoads strides of every
+    // component together and only then adds them, in the same order (the
+    // padding zeros leave a sum that starts at +0 unchanged).
+    constexpr int kFinLoads = 4;
     __shared__ double sh[kFinThreads / kWave][kMaxPartials];
     const int t = threadIdx.x;
     double acc[kMaxPartials];
 #pragma unroll
-    for (int c = 0; c < kMaxPartials; ++c) {
-        acc[c] = 0.0;
-        if (c < ncomp)
-            for (int q = t; q < nb; q += kFinThreads) acc[c] += partial[(long long)c * nb + q];
+    for (int c = 0; c < kMaxPartials; ++c) acc[c] = 0.0;
+    for (int q0 = t; q0 < nb; q0 += kFinThreads * kFinLoads) {
+        double v[kMaxPartials][kFinLoads];
+#pragma unroll
+        for (int c = 0; c < kMaxPartials; ++c)
+#pragma unroll
+            for (int u = 0; u < kFinLoads; ++u) {
+                const int q = q0 + u * kFinThreads;
+                v[c][u] = (c < ncomp && q < nb) ? partial[(long long)c * nb + q] : 0.0;
+            }
+#pragma unroll
+        for (int c = 0; c < kMaxPartials; ++c)
+#pragma unroll
+            for (int u = 0; u < kFinLoads; ++u) acc[c] += v[c][u];
     }
 #pragma unroll
     for (int c = 0; c < kMaxPartials; ++c)
@@ -1299,12 +1314,15 @@ __device__ __forceinline__ void finish_body(int which, DevScalars *sc, const dou
     // the start-of-solve and end-of-solve finishers run whatever the done flag says
     const bool always = which == kFinInit || which == kFinTrue || which == kFinOuter || which == kFinInner ||
                         which == kFinResume;
-    if (!always && sc->done) return;
+    // The flag is read before the sums (whose loads then need not wait for
+    // it) and tested after them; the sums of a finished solve are not used.
+    const int done = sc->done;
     double s[kMaxPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     const int ncomp = (which == kFinSigma) ? 1
                       : (which == kFinSweep) ? 5
                       : ((which == kFinInit || which == kFinOuter) ? 3 : 2);   // kFinLineInit: 2
     block_sums(partial, nb, ncomp, s);
+    if (!always && done) return;
     if (threadIdx.x != 0) return;
     if (which == kFinInit) {
         // After r = b - A x0: rho = r.z, ||b||, first residual check.
