@@ -940,7 +940,7 @@ template <int R, typename V>
 struct alignas(16) SweepLds {   // 16: the coefficient rows are read 16 bytes at a time
     alignas(16) V lp[3][kWaves * R][kWave];     // p_{j-1} of three layers
     alignas(16) V lq[3][kWaves * R][kWave];     // p_j of three layers
-    alignas(16) double lc[3][kWaves * R][8];    // row coefficients of three layers
+    alignas(16) V lc[3][kWaves * R][8];         // row coefficients of three layers, converted to V
     double red[kWaves][5];
 };
 template <int R, typename V>
@@ -1054,7 +1054,9 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     };
     // Row coefficients of the box rows of one layer, staged in LDS (three
     // layers in rotation) and read back as broadcasts: rm rp tm tp s pq.
-    // load_coef returns this thread's value; put_coef writes it a step later.
+    // load_coef returns this thread's value; put_coef writes it a step later,
+    // converted once to the vectors' type (FP32 sweeps then read floats and
+    // convert nothing per cell).
     auto load_coef = [&](int a) -> double {
         const int t = threadIdx.x;
         double v = 0.0;
@@ -1069,31 +1071,26 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
     };
     auto put_coef = [&](int a, double v) {
         const int t = threadIdx.x;
-        if (t < ER * 8) lc[slot(a)][t >> 3][t & 7] = v;
+        if (t < ER * 8) lc[slot(a)][t >> 3][t & 7] = (V)v;
     };
-    auto coef = [&](int sl, int e) -> RowCoef {
-        RowCoef r;
-        r.rm = lc[sl][e][0];
-        r.rp = lc[sl][e][1];
-        r.tm = lc[sl][e][2];
-        r.tp = lc[sl][e][3];
-        r.s = lc[sl][e][4];
-        r.pq = lc[sl][e][5];
-        r.pad0 = r.pad1 = 0.0;
-        return r;
+    struct Coef {
+        V rm, rp, tm, tp, s, pq;
+    };
+    auto coef = [&](int sl, int e) -> Coef {
+        return Coef{lc[sl][e][0], lc[sl][e][1], lc[sl][e][2], lc[sl][e][3], lc[sl][e][4], lc[sl][e][5]};
     };
     // 7-point operator at one cell from the centre, radial and theta
     // neighbours; the phi neighbours come from the adjacent lanes.
-    auto apply = [&](const RowCoef &rc, V pc, V pim, V pip, V pjm, V pjp) -> V {
+    auto apply = [&](const Coef &rc, V pc, V pim, V pip, V pjm, V pjp) -> V {
         const V pkm = shr1(pc), pkp = shl1(pc);
-        V t = (V)rc.s * pc;
-        t = vfma<V>(-(V)rc.rm, pim, t);
-        t = vfma<V>(-(V)rc.rp, pip, t);
-        t = vfma<V>(-(V)rc.tm, pjm, t);
-        t = vfma<V>(-(V)rc.tp, pjp, t);
+        V t = rc.s * pc;
+        t = vfma<V>(-rc.rm, pim, t);
+        t = vfma<V>(-rc.rp, pip, t);
+        t = vfma<V>(-rc.tm, pjm, t);
+        t = vfma<V>(-rc.tp, pjp, t);
         V u = ihm * (pc - pkm);
         u = vfma<V>(ihk, pc - pkp, u);
-        return vfma<V>(dph, t, (V)rc.pq * u);
+        return vfma<V>(dph, t, rc.pq * u);
     };
 
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
@@ -1117,12 +1114,12 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             const int e = e0 + m;
-            const RowCoef rc = coef(sa, e);
+            const Coef rc = coef(sa, e);
             const V pc = lp[sa][e][lane];
             const V ap = apply(rc, pc, lp[sb][e][lane], lp[sa1][e][lane], lp[sa][max(e - 1, 0)][lane],
                                lp[sa][min(e + 1, ER - 1)][lane]);
             const V rn = vfma<V>(-alpha, ap, rv[m]);
-            const V inv = recip(vfma<V>(dph, (V)rc.s, (V)rc.pq * ihs));
+            const V inv = recip(vfma<V>(dph, rc.s, rc.pq * ihs));
             const V zn = rn * inv;
             const V qn = vfma<V>(beta, pc, zn);
             qa[m] = qn;
@@ -1146,7 +1143,7 @@ __device__ __forceinline__ void sweep_body(const GridArgs &g, const SweepVecs<V>
             for (int m = 0; m < R; ++m) {
                 if (!oki[m]) continue;   // uniform
                 const int e = e0 + m;
-                const RowCoef rc = coef(sb, e);
+                const Coef rc = coef(sb, e);
                 const V qc = lq[sb][e][lane];
                 const V wv = apply(rc, qc, lq[sb2][e][lane], qa[m], lq[sb][e - 1][lane], lq[sb][e + 1][lane]);
                 if (col_in) {
