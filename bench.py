@@ -131,7 +131,7 @@ def kernel_name(stats, which):
     if which in xm:
         return f"stencil_sweep<{stats['sweep_rows']},double,{xm[which]}>"
     tile = stats["tile_p"] if which == "update_p" else stats["tile_r"]
-    mode = 2 if which == "update_p" else 3
+    mode = "2" if which == "update_p" else "4|5"   # the r/x update alternates its two pairing modes
     if tile > 100:
         return f"stencil_wave<{tile - 100},{mode},double>"
     return f"stencil_march<{tile},{mode},double>"

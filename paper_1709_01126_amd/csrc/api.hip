@@ -283,22 +283,26 @@ int resident_blocks(const pot3d_ctx *c, int mode, int tile)
 
 // Default shapes (measured on MI355X at 151 x 301 x 601).  The p update runs
 // on 16-row LDS-plane tiles (it reads r and p_old over a halo ring, and a
-// taller tile reads fewer halo rows per cell); the FP64 r/x update on 8-row
-// LDS-plane tiles.  FP64 launches about 3 workgroups per CU, in long radial
-// chunks: fewer, longer chunks repeat fewer boundary layers, and a launch
-// that fits the resident slots runs as one wave of workgroups with no tail.
+// taller tile reads fewer halo rows per cell), about 3 workgroups per CU in
+// long radial chunks: fewer, longer chunks repeat fewer boundary layers, and
+// a launch that fits the resident slots runs as one wave of workgroups with
+// no tail.  The FP64 r/x update, whose x update comes once per pair of
+// iterations, runs on the four-row wavefront kernel with about 4096
+// workgroups: two-pass solve 1.906 s against 2.025 s on 8-row LDS-plane
+// tiles, phi-line solve 0.966 s against 0.998 s.
 // FP32 passes move half the bytes per cell, so a workgroup keeps fewer bytes
 // in flight and more are needed: the p update about 6 per CU, the r/x update
 // on the two-row wavefront kernel with about 4096 workgroups.  (The 8-row
 // LDS-plane FP32 r/x update is as fast in a single solve, but ran 18 % slower
-// in the batched launches of the server; the wavefront kernel 3 %.)  FP64
-// iteration: 346 us against 368 us with 8-row tiles for both passes.
+// in the batched launches of the server; the wavefront kernel 3 %.)  The
+// 16-row p update took the FP64 two-pass iteration, with x in every r/x
+// update, from 368 us on 8-row tiles for both passes to 346 us.
 // POT3D_TILE[_P|_R] and POT3D_TARGET_BLOCKS[_P|_R] override.
 void default_tiles(int precision, int *tile_p, int *tile_r)
 {
     const int all = valid_tile(env_int("POT3D_TILE", 0), 0);
     const int dflt_p = kTileMarch16;
-    const int dflt_r = precision == POT3D_FP32_REFINED ? kTileWave2 : kTileMarch8;
+    const int dflt_r = precision == POT3D_FP32_REFINED ? kTileWave2 : kTileWave4;
     *tile_p = valid_tile(env_int("POT3D_TILE_P", all ? all : dflt_p), dflt_p);
     *tile_r = valid_tile(env_int("POT3D_TILE_R", all ? all : dflt_r), dflt_r);
 }

@@ -19,13 +19,14 @@ using pot3d::StencilVecs;
 using pot3d::kTileMarch16;
 using pot3d::kTileMarch8;
 using pot3d::kTileWave2;
+using pot3d::kTileWave4;
 
 struct pot3d_ctx {
     int device = 0;
     int nr = 0, nt = 0, np = 0, pitch = 0;
     long long n = 0, npad = 0;
     int precision = POT3D_FP64;
-    int tile_p = kTileMarch16, tile_r = kTileMarch8, tile_o = kTileWave2;   // set by choose_launch
+    int tile_p = kTileMarch16, tile_r = kTileWave4, tile_o = kTileWave2;   // set by choose_launch
     int max_blocks = 0;
     int num_cu = 256;
     int graph_m = 16;
