@@ -193,7 +193,7 @@ def test_x_every_other_sweep_matches_every_sweep(case, monkeypatch):
     got = {}
     for mode in ("2", "1"):
         monkeypatch.setenv("POT3D_SWEEP_X", mode)
-        with P.Solver(rf, tf, pf) as s:
+        with P.Solver(rf, tf, pf, iteration=P.ITER_ONE_SWEEP) as s:
             got[mode] = [gpu_solve(s, br, tol, K) for tol, K in runs]
             assert s.stats()["bytes_per_iter"] == (40.0 if mode == "2" else 48.0) * s.stats()["n"]
     for (tol, K), a, b in zip(runs, got["2"], got["1"]):
