@@ -56,6 +56,29 @@ def test_refined_reaches_fp64_residual(case, iteration):
     assert e2 <= 1e-7 and emax <= 1e-7
 
 
+@pytest.mark.parametrize("env", [{"POT3D_SWEEP_CI": "1"}, {"POT3D_SWEEP_CI": "3"}, {"POT3D_SWEEP_TK": "16"},
+                                 {"POT3D_SWEEP_ROWS": "6"}, {"POT3D_SWEEP_X": "1"}])
+def test_refined_sweep_shapes(env, monkeypatch):
+    """FP32 sweeps (which load p two layers ahead) over radial chunks of one
+    and three layers, narrow tiles, taller boxes and x in every sweep: each
+    reaches the FP64 residual and the oracle's Phi like the default shape."""
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    case = GRIDS[4]
+    rf, tf, pf = make_faces(*case)
+    br = magnetograms.br_bipoles(tf, pf, 40, seed=3)
+    tol = 1e-10
+    ref = oracle.solve(rf, tf, pf, br, tol, 100_000)
+    with P.Solver(rf, tf, pf, precision=P.FP32_REFINED, iteration=P.ITER_ONE_SWEEP) as s:
+        phi, st, it, rr = refined_solve(s, br, tol, 200_000)
+        stats = s.stats()
+    tr = oracle.true_relres(ref["coef"], ref["b"], phi)
+    e2 = np.linalg.norm(phi - ref["phi"]) / np.linalg.norm(ref["phi"])
+    print(f"[refined shape] {env} chunk={stats['chunk_s']} blocks={stats['blocks_s']} inner iters={it} "
+          f"true_relres={tr:.2e} err2={e2:.2e}", flush=True)
+    assert st == P.OK and tr <= tol * 1.01 and e2 <= 1e-7
+
+
 def test_refined_small_workload_and_poles():
     rf, tf, pf = SMALL.faces()
     br = SMALL.br((rf, tf, pf))
